@@ -1,0 +1,386 @@
+// kmc_api.hip -- host runtime of libkmc.so: the C ABI declared in kmc.h.
+//
+// Parameter validation, workspace layout, kernel launch plan, optional
+// hipGraph capture of one step, read-back, statistics.  The library never
+// allocates device memory: everything lives in the caller's workspace.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "kmc_internal.h"
+
+using namespace kmc;
+
+struct kmc_ctx {
+    Plan plan{};
+    kmc_config cfg{};
+    std::vector<kmc_box> boxes;
+    int device = 0;
+    bool stepped = false;
+    // graph replay
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // profile mode: one set of phase events per step, folded in get_stats
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::vector<hipEvent_t>> ev_pending;
+    double ms[8] = {0};
+    uint64_t timed_steps = 0;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+int check_box(const kmc_box& b)
+{
+    if (b.geometry != KMC_GEOM_BOX && b.geometry != KMC_GEOM_SPHERE) return KMC_EINVAL;
+    if (!finite_pos(b.D2) || !finite_pos(b.dt)) return KMC_EINVAL;
+    const double D = std::sqrt(b.D2);
+    for (int k = 0; k < 3; ++k) {
+        if (b.bc[k] != KMC_BC_REFLECT && b.bc[k] != KMC_BC_PERIODIC) return KMC_EINVAL;
+        if (b.ncell[k] < 1) return KMC_EINVAL;
+        if (b.bc[k] == KMC_BC_PERIODIC && b.ncell[k] < 3) return KMC_EINVAL;
+        if (!std::isfinite(b.lo[k]) || !std::isfinite(b.hi[k]) || !(b.hi[k] > b.lo[k])) return KMC_EINVAL;
+        if (!finite_pos(b.inv_h[k])) return KMC_EINVAL;
+        // the 27-cell neighbourhood must contain every point closer than D
+        if (b.inv_h[k] * D > 1.0 + 1e-9) return KMC_EINVAL;
+        if (b.geometry == KMC_GEOM_SPHERE) {
+            if (b.bc[k] != KMC_BC_REFLECT) return KMC_EINVAL;
+            if (!finite_pos(b.sphere_r) || b.lo[k] > -b.sphere_r || b.hi[k] < b.sphere_r) return KMC_EINVAL;
+        }
+    }
+    return KMC_OK;
+}
+
+int check_cfg(const kmc_config& c)
+{
+    if (c.precision != KMC_FP64 && c.precision != KMC_FP32_SCREEN) return KMC_EINVAL;
+    if (c.kinematics != KMC_KIN_AT_TSTAR && c.kinematics != KMC_KIN_VEL_ONLY) return KMC_EINVAL;
+    if (c.block_size != 0 && (c.block_size < 64 || c.block_size > 1024 || c.block_size % 64 != 0)) return KMC_EINVAL;
+    if (c.use_graph != 0 && c.use_graph != 1) return KMC_EINVAL;
+    if (c.profile != 0 && c.profile != 1) return KMC_EINVAL;
+    for (int r : c.reserved)
+        if (r != 0) return KMC_EINVAL;
+    return KMC_OK;
+}
+
+struct Totals {
+    uint64_t N = 0, C = 0;
+};
+
+int totals(const kmc_box* boxes, uint32_t nboxes, Totals& t)
+{
+    for (uint32_t b = 0; b < nboxes; ++b) {
+        t.N += boxes[b].n;
+        t.C += (uint64_t)boxes[b].ncell[0] * (uint64_t)boxes[b].ncell[1] * (uint64_t)boxes[b].ncell[2];
+    }
+    if (t.N > 0x7FFFFFFFull) return KMC_EOVERFLOW;
+    if (t.C > 0xFFFFFFFEull) return KMC_EOVERFLOW;
+    return KMC_OK;
+}
+
+int validate(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, Totals& t)
+{
+    if (!boxes || !cfg || nboxes == 0) return KMC_EINVAL;
+    for (uint32_t b = 0; b < nboxes; ++b) {
+        int rc = check_box(boxes[b]);
+        if (rc != KMC_OK) return rc;
+    }
+    int rc = check_cfg(*cfg);
+    if (rc != KMC_OK) return rc;
+    return totals(boxes, nboxes, t);
+}
+
+uint32_t history_len(const kmc_config& c) { return c.history ? c.history : 1024u; }
+
+// Carve the workspace; with base == nullptr only the size is computed.
+size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const Totals& t)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        char* ptr = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return ptr;
+    };
+    const size_t N = t.N, C = t.C;
+    const uint32_t H = history_len(cfg);
+    const uint32_t nblk = (uint32_t)((C + kScanTile - 1) / kScanTile);
+    const bool f32 = cfg.precision == KMC_FP32_SCREEN;
+    const uint32_t cap = f32 ? (cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N) : 0u;
+    p.ctl = (Ctl*)take(sizeof(Ctl));
+    p.boxes = (BoxDev*)take(sizeof(BoxDev) * nboxes);
+    p.hist_np = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
+    p.hist_dig = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
+    p.A = (double*)take(sizeof(double) * 6 * N);
+    p.B = (double*)take(sizeof(double) * 6 * N);
+    p.B32 = f32 ? (float*)take(sizeof(float) * 6 * N) : nullptr;
+    p.idA = (uint32_t*)take(4 * N);
+    p.idB = (uint32_t*)take(4 * N);
+    p.cell = (uint32_t*)take(4 * N);
+    p.slot = (uint32_t*)take(4 * N);
+    p.partner = (int32_t*)take(4 * N);
+    p.boxidx = nboxes > 1 ? (uint32_t*)take(4 * N) : nullptr;
+    p.count = (uint32_t*)take(4 * C);
+    p.start = (uint32_t*)take(4 * (C + 1));
+    p.partial = (uint32_t*)take(4 * (size_t)(nblk ? nblk : 1));
+    p.recheck = f32 ? (uint32_t*)take(4 * (size_t)(cap ? cap : 1)) : nullptr;
+    p.N = (uint32_t)N;
+    p.C = (uint32_t)C;
+    p.nboxes = nboxes;
+    p.H = H;
+    p.nblk_scan = nblk;
+    p.recheck_cap = cap;
+    p.seed = cfg.seed;
+    p.precision = cfg.precision;
+    p.kinematics = cfg.kinematics;
+    p.block = cfg.block_size ? cfg.block_size : 256;
+    return off;
+}
+
+void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
+{
+    std::memset(&d, 0, sizeof(d));
+    for (int k = 0; k < 3; ++k) {
+        d.lo[k] = b.lo[k];
+        d.hi[k] = b.hi[k];
+        d.L[k] = b.hi[k] - b.lo[k];
+        d.inv_h[k] = b.inv_h[k];
+        d.nc[k] = b.ncell[k];
+        d.periodic[k] = b.bc[k] == KMC_BC_PERIODIC ? 1 : 0;
+        d.ctr32[k] = (float)(0.5 * (b.lo[k] + b.hi[k]));
+        d.L32[k] = (float)d.L[k];
+    }
+    d.D2 = b.D2;
+    d.dt = b.dt;
+    d.sphere = b.geometry == KMC_GEOM_SPHERE ? 1 : 0;
+    d.R = b.sphere_r;
+    d.R2 = b.sphere_r * b.sphere_r;
+    d.coff = coff;
+    d.poff = poff;
+    d.n = b.n;
+    d.D2_32 = (float)b.D2;
+    d.dt_32 = (float)b.dt;
+}
+
+int dev_err(hipError_t e) { return e == hipSuccess ? KMC_OK : KMC_EDEVICE; }
+
+void fold_events(kmc_ctx* c)
+{
+    for (auto& set : c->ev_pending) {
+        for (int k = 0; k < KMC_PHASE_COUNT; ++k) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, set[k], set[k + 1]) == hipSuccess) c->ms[k] += ms;
+        }
+        c->timed_steps += 1;
+        for (auto e : set) c->ev_free.push_back(e);
+    }
+    c->ev_pending.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+int kmc_abi_version(void) { return KMC_ABI_VERSION; }
+
+const char* kmc_strerror(int status)
+{
+    switch (status) {
+    case KMC_OK: return "ok";
+    case KMC_EINVAL: return "invalid argument";
+    case KMC_ENOMEM: return "workspace too small or host allocation failed";
+    case KMC_EDEVICE: return "HIP runtime error";
+    case KMC_EOVERFLOW: return "size exceeds the library's index range";
+    case KMC_ESTATE: return "call not valid in the current state";
+    default: return "unknown status";
+    }
+}
+
+int kmc_workspace_bytes(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, size_t* bytes)
+{
+    if (!bytes) return KMC_EINVAL;
+    Totals t;
+    int rc = validate(boxes, nboxes, cfg, t);
+    if (rc != KMC_OK) return rc;
+    Plan p;
+    *bytes = layout(p, nullptr, nboxes, *cfg, t);
+    return KMC_OK;
+}
+
+int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,
+             void* d_workspace, size_t workspace_bytes, void* stream, kmc_ctx** out)
+{
+    if (!out || !d_workspace) return KMC_EINVAL;
+    *out = nullptr;
+    Totals t;
+    int rc = validate(boxes, nboxes, cfg, t);
+    if (rc != KMC_OK) return rc;
+    if (t.N > 0 && !d_state) return KMC_EINVAL;
+    if ((uintptr_t)d_workspace % kAlign != 0) return KMC_EINVAL;
+    Plan probe;
+    const size_t need = layout(probe, nullptr, nboxes, *cfg, t);
+    if (workspace_bytes < need) return KMC_ENOMEM;
+
+    kmc_ctx* c = new (std::nothrow) kmc_ctx();
+    if (!c) return KMC_ENOMEM;
+    c->cfg = *cfg;
+    c->boxes.assign(boxes, boxes + nboxes);
+    layout(c->plan, (char*)d_workspace, nboxes, *cfg, t);
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return KMC_EDEVICE; }
+
+    std::vector<BoxDev> bd(nboxes);
+    uint64_t coff = 0, poff = 0;
+    for (uint32_t b = 0; b < nboxes; ++b) {
+        fill_box_dev(bd[b], boxes[b], (uint32_t)coff, (uint32_t)poff);
+        coff += (uint64_t)boxes[b].ncell[0] * boxes[b].ncell[1] * boxes[b].ncell[2];
+        poff += boxes[b].n;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(c->plan.boxes, bd.data(), sizeof(BoxDev) * nboxes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_init(c->plan, d_state, s);
+    if (e == hipSuccess) {
+        // the step counter starts at step0 (k_init_ctl wrote 0)
+        unsigned long long step0 = cfg->step0;
+        e = hipMemcpyAsync(&c->plan.ctl->step, &step0, sizeof(step0), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // step0 lives on this stack frame
+    }
+    if (e != hipSuccess) { delete c; return KMC_EDEVICE; }
+    *out = c;
+    return KMC_OK;
+}
+
+int kmc_step(kmc_ctx* c, uint32_t nsteps, void* stream)
+{
+    if (!c) return KMC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    if (nsteps == 0) return KMC_OK;
+    const bool graph = c->cfg.use_graph && !c->cfg.profile;
+    if (graph && !c->exec) {
+        if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return KMC_EDEVICE;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_step(c->plan, c->cap_stream, nullptr);
+            e = hipStreamEndCapture(c->cap_stream, &c->graph);
+            if (e == hipSuccess && le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) return KMC_EDEVICE;
+    }
+    for (uint32_t k = 0; k < nsteps; ++k) {
+        hipError_t e;
+        if (graph) {
+            e = hipGraphLaunch(c->exec, s);
+        } else if (c->cfg.profile) {
+            std::vector<hipEvent_t> set(KMC_PHASE_COUNT + 1);
+            for (auto& ev : set) {
+                if (!c->ev_free.empty()) { ev = c->ev_free.back(); c->ev_free.pop_back(); }
+                else if (hipEventCreate(&ev) != hipSuccess) return KMC_EDEVICE;
+            }
+            e = launch_step(c->plan, s, set.data());
+            c->ev_pending.push_back(std::move(set));
+        } else {
+            e = launch_step(c->plan, s, nullptr);
+        }
+        if (e != hipSuccess) return KMC_EDEVICE;
+    }
+    c->stepped = true;
+    return KMC_OK;
+}
+
+int kmc_read_partners(kmc_ctx* c, int32_t* d_partner_by_id, void* stream)
+{
+    if (!c || (!d_partner_by_id && c->plan.N > 0)) return KMC_EINVAL;
+    if (!c->stepped) return KMC_ESTATE;
+    return dev_err(launch_read_partners(c->plan, d_partner_by_id, (hipStream_t)stream));
+}
+
+int kmc_read_state(kmc_ctx* c, double* d_state_by_id, void* stream)
+{
+    if (!c || (!d_state_by_id && c->plan.N > 0)) return KMC_EINVAL;
+    return dev_err(launch_read_state(c->plan, d_state_by_id, (hipStream_t)stream));
+}
+
+int kmc_read_history(kmc_ctx* c, uint64_t* h_npairs, uint64_t* h_digest, uint32_t capacity,
+                     uint32_t* count, void* stream)
+{
+    if (!c || !count || (capacity > 0 && (!h_npairs || !h_digest))) return KMC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const Plan& p = c->plan;
+    Ctl ctl;
+    std::vector<unsigned long long> np((size_t)p.H * kHistLanes), dg((size_t)p.H * kHistLanes);
+    hipError_t e = hipMemcpyAsync(&ctl, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(np.data(), p.hist_np, np.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dg.data(), p.hist_dig, dg.size() * 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return KMC_EDEVICE;
+    uint64_t avail = ctl.steps_done < p.H ? ctl.steps_done : p.H;
+    if (avail > capacity) avail = capacity;
+    for (uint64_t k = 0; k < avail; ++k) {
+        const uint64_t step = ctl.steps_done - avail + k;
+        const size_t row = (size_t)(step % p.H) * kHistLanes;
+        uint64_t a = 0, d = 0;
+        for (int l = 0; l < kHistLanes; ++l) { a += np[row + l]; d += dg[row + l]; }
+        h_npairs[k] = a;
+        h_digest[k] = d;
+    }
+    *count = (uint32_t)avail;
+    return KMC_OK;
+}
+
+int kmc_count_pair_tests(kmc_ctx* c, uint64_t* h_pair_tests, void* stream)
+{
+    if (!c || !h_pair_tests) return KMC_EINVAL;
+    if (!c->stepped) return KMC_ESTATE;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long* d = &c->plan.ctl->scratch;
+    unsigned long long h = 0;
+    hipError_t e = hipMemsetAsync(d, 0, sizeof(h), s);
+    if (e == hipSuccess) e = launch_count_tests(c->plan, d, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return KMC_EDEVICE;
+    *h_pair_tests = h;
+    return KMC_OK;
+}
+
+int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
+{
+    if (!c || !out) return KMC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    Ctl ctl;
+    hipError_t e = hipMemcpyAsync(&ctl, c->plan.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return KMC_EDEVICE;
+    fold_events(c);
+    std::memset(out, 0, sizeof(*out));
+    out->steps = ctl.steps_done;
+    out->n_total = c->plan.N;
+    out->cells_total = c->plan.C;
+    out->rechecks = ctl.rechecks_total;
+    out->fallbacks = ctl.fallbacks_total;
+    for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
+    out->timed_steps = c->timed_steps;
+    return KMC_OK;
+}
+
+void kmc_destroy(kmc_ctx* c)
+{
+    if (!c) return;
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (auto& set : c->ev_pending)
+        for (auto e : set) (void)hipEventDestroy(e);
+    for (auto e : c->ev_free) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// kmc_internal.h -- structures shared by the host runtime (kmc_api.hip) and
+// the gfx950 kernels (kmc_device.hip) of libkmc.so.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kmc.h"
+
+namespace kmc {
+
+// Threads per block of the streaming kernels and of the three-pass scan.
+constexpr int kScanBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanBlock * kScanItems;
+// Partial sums per history row (spreads the per-step count/digest atomics).
+constexpr int kHistLanes = 64;
+
+// Device copy of one box.  All derived scalars are computed once on the host
+// (L = hi - lo, R2 = R*R) so that every kernel sees the same bits.
+struct alignas(16) BoxDev {
+    double lo[3], hi[3], L[3], inv_h[3];
+    double D2, dt, R, R2;
+    int32_t nc[3];
+    int32_t periodic[3];
+    int32_t sphere;
+    uint32_t coff;       // first global cell of the box
+    uint32_t poff;       // first global particle index of the box
+    uint32_t n;          // particles in the box
+    // FP32 screen constants (see the screen kernel for their meaning)
+    float ctr32[3];      // origin of the FP32 position copy
+    float L32[3];        // periodic shift lengths, rounded to FP32
+    float D2_32, dt_32;  // thresholds rounded to FP32
+    float eps_r, eps_v;  // absolute input-rounding bounds of positions/velocities
+    float rmax, vmax;    // magnitude bounds used by the error terms
+    float pad_[2];
+};
+
+// Per-context control block in device memory.
+struct Ctl {
+    unsigned long long step;            // global index of the next step
+    unsigned long long steps_done;      // steps completed since init
+    unsigned long long rechecks_total;  // FP32 screen: particles re-searched
+    unsigned long long fallbacks_total; // FP32 screen: list overflows
+    unsigned long long scratch;         // target of host-requested reductions
+    unsigned int recheck_count;         // this step's recheck list length
+    unsigned int overflow;              // this step's overflow flag
+    unsigned int work_next;             // work-queue head of persistent kernels
+    unsigned int pad_[5];
+};
+
+// Device pointers carved out of the caller's workspace plus launch scalars.
+struct Plan {
+    Ctl* ctl;
+    BoxDev* boxes;
+    unsigned long long* hist_np;   // [history][kHistLanes]
+    unsigned long long* hist_dig;  // [history][kHistLanes]
+    double* A;                     // current state, 6*N SoA (previous cell order)
+    double* B;                     // cell-sorted copy of the current state, 6*N
+    float* B32;                    // FP32 screen copy of B (positions, velocities), 6*N
+    uint32_t* idA;
+    uint32_t* idB;
+    uint32_t* cell;                // per particle in A order: global cell
+    uint32_t* slot;                // per particle in A order: rank inside its cell
+    int32_t* partner;              // per sorted particle: sorted index of partner or -1
+    uint32_t* boxidx;              // per particle: its box (null when there is one box)
+    uint32_t* count;               // per cell: particles (zero between steps)
+    uint32_t* start;               // per cell + 1: exclusive prefix of count
+    uint32_t* partial;             // scan block sums
+    uint32_t* recheck;             // FP32 screen: sorted indices to re-search in FP64
+    uint32_t N, C, nboxes, H;
+    uint32_t nblk_scan;
+    uint32_t recheck_cap;
+    uint64_t seed;
+    int32_t precision, kinematics, block;
+};
+
+// Kernel launchers (kmc_device.hip).  `ev`, when not null, points to
+// KMC_PHASE_COUNT + 1 events recorded on `s` at the phase boundaries.
+hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s);
+hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev);
+hipError_t launch_read_partners(const Plan& p, int32_t* out, hipStream_t s);
+hipError_t launch_read_state(const Plan& p, double* out, hipStream_t s);
+hipError_t launch_count_tests(const Plan& p, unsigned long long* d_out, hipStream_t s);
+
+}  // namespace kmc

@@ -220,10 +220,13 @@ def c4_batch(nboxes=256, n_lo=1e3, n_hi=1e5, ensemble_seed=4, kappa=1.0, steps=5
                     info=dict(kappa=kappa, nboxes=nboxes))
 
 
-def c5_blobs(n=10_000_000, nblobs=64, D=3.0e-3, ic_seed=5, steps=50, seed=1):
+def c5_blobs(n=10_000_000, nblobs=64, D=None, ic_seed=5, steps=50, seed=1):
     """64 isotropic Gaussian blobs (centres uniform, widths log-uniform in
     [0.005, 0.05]) in a periodic unit cube; bulk blob velocity N(0, 0.5^2)
-    plus thermal N(0, 0.1^2)."""
+    plus thermal N(0, 0.1^2).  D = 3e-3 at N = 1e7, scaled as N^(-1/3) for
+    other N (same particles per cell)."""
+    if D is None:
+        D = 3.0e-3 * (1e7 / n) ** (1.0 / 3.0)
     rng = np.random.default_rng(ic_seed)
     centres = rng.random((nblobs, 3))
     widths = np.exp(rng.uniform(math.log(0.005), math.log(0.05), nblobs))

@@ -1,0 +1,109 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/kmc.h declares, and its host-side validation (kmc_workspace_bytes,
+which touches no device) rejects invalid boxes and configurations."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1310_3437_amd import inputs as I
+from paper_1310_3437_amd import kmc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "kmc.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(kmc_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = kmc.load()
+    names = _declared()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(kmc.EXPORTS)
+    assert L.kmc_abi_version() == 1
+
+
+def test_struct_sizes_match_header():
+    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 72 bytes
+    assert C.sizeof(kmc.KmcBox) == 128
+    assert C.sizeof(kmc.KmcConfig) == 72
+    assert C.sizeof(kmc.KmcStats) == 112
+
+
+def _ws(boxes, **cfg):
+    arr = kmc.make_boxes(boxes)
+    c = kmc.make_config(**cfg)
+    n = C.c_size_t(0)
+    return kmc.load().kmc_workspace_bytes(arr, len(boxes), C.byref(c), C.byref(n)), n.value
+
+
+def test_workspace_size_scales_with_particles_and_cells():
+    w = I.c1_small()
+    rc, n1 = _ws(w.boxes)
+    assert rc == 0 and n1 > 4096 * 100
+    rc, n2 = _ws(w.boxes, precision=kmc.KMC_FP32_SCREEN)
+    assert rc == 0 and n2 > n1
+    big = I.Box(n=10_000_000, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(300, 300, 300),
+                periodic=(True,) * 3, D2=1e-6, dt=1e-3)
+    rc, n3 = _ws([big])
+    assert rc == 0 and n3 >= 10_000_000 * 116 + 27_000_000 * 8
+
+
+def _good():
+    return I.Box(n=100, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(4, 4, 4), periodic=(True,) * 3,
+                 D2=0.2 ** 2, dt=0.01)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda b: setattr(b, "D2", 0.0),
+    lambda b: setattr(b, "dt", -1.0),
+    lambda b: setattr(b, "dt", float("nan")),
+    lambda b: setattr(b, "ncell", (2, 4, 4)),          # periodic axis with < 3 cells
+    lambda b: setattr(b, "ncell", (0, 4, 4)),
+    lambda b: setattr(b, "hi", (-0.5, 1, 1)),          # negative extent
+    lambda b: setattr(b, "D2", 0.3 ** 2),              # cell edge 0.25 < D
+    lambda b: (setattr(b, "sphere", True), setattr(b, "R", 0.5)),   # sphere with periodic axes
+])
+def test_invalid_boxes_rejected(mutate):
+    b = _good()
+    assert _ws([b])[0] == 0
+    mutate(b)
+    assert _ws([b])[0] == kmc.KMC_EINVAL
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(precision=7), dict(kinematics=3), dict(block_size=100), dict(block_size=2048),
+])
+def test_invalid_configs_rejected(cfg):
+    assert _ws([_good()], **cfg)[0] == kmc.KMC_EINVAL
+
+
+def test_reserved_config_words_must_be_zero():
+    arr = kmc.make_boxes([_good()])
+    c = kmc.make_config()
+    c.reserved[3] = 1
+    n = C.c_size_t(0)
+    assert kmc.load().kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
+
+
+def test_too_many_particles_overflow():
+    b = _good()
+    b.n = 2 ** 32 - 1
+    bb = _good()
+    assert _ws([b, bb])[0] == kmc.KMC_EOVERFLOW
+
+
+def test_null_arguments():
+    L = kmc.load()
+    c = kmc.make_config()
+    n = C.c_size_t(0)
+    assert L.kmc_workspace_bytes(None, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
+    assert L.kmc_workspace_bytes(kmc.make_boxes([_good()]), 0, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
+    assert L.kmc_strerror(-1) == b"invalid argument"
+    L.kmc_destroy(None)
