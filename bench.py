@@ -1,0 +1,208 @@
+"""Benchmark of the DCA collision step on one MI355X.
+
+Workload (the headline configuration): N = 1e8 particles uniform in a ball
+of radius 1 with radial infall v = -0.5 x + N(0, 0.1^2), reflecting sphere,
+399^3 cells of edge ~D (about three particles per cell), seeded synthetic
+input.  The plain FP64 path and the FP32-screen path each run W untimed and K
+timed steps from the same initial state; their per-step pair counts and
+digests must be identical.  `value` is the FP32-screen path's particle-steps/s
+when that path is built, else the FP64 path's.
+
+Per-phase times come from HIP events the library records on the launch
+stream around every phase (profile mode).  The roofline object describes the
+dominant kernel (the partner search).  `cpu_baseline` times the CPU oracle
+(test infrastructure) on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s at N=1e8 (FP32-screen vs plain FP64, identical pair lists)"
+# Algorithmic floating-point operations of one pair test (an FMA counts 2):
+# r, g: 6 subtractions; b, g2: 2 x (1 mul + 2 fma) = 10; c = r x g: 3 x
+# (1 mul + 1 fma) = 9; c2: 1 mul + 2 fma = 5; dt*g2, D2*g2: 2.
+FLOP_PER_PAIR_TEST = 32
+PEAK_VALU_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 flop x 2.4 GHz (FP64, or unpacked FP32)
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kmc_device.hip", "kmc_internal.h"):
+        with open(os.path.join(ROOT, "paper_1310_3437_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(path_name, launches_bytes):
+    """HBM traffic measured by rocprofv3 counters for the current kernel
+    source, if a committed summary exists for it (else None)."""
+    f = os.path.join(ROOT, "profiles", "search_traffic.json")
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        d = json.load(fh)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    e = d.get(path_name)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def run_path(kmc, w, precision, steps, warmup, pair_tests):
+    import torch
+    name = "fp64" if precision == kmc.KMC_FP64 else "fp32_screen"
+    log(f"[bench] {name}: init N={w.n}")
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=precision,
+                  history=max(64, steps + warmup), profile=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    s0 = sim.stats()
+    if pair_tests is None:
+        pair_tests = sim.pair_tests()
+    log(f"[bench] {name}: warmup done, timing {steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s1 = sim.stats()
+    hn, hd = sim.history()
+    ms_phase = {k: (s1["ms"][k] - s0["ms"][k]) / steps for k in s1["ms"]}
+    out = dict(
+        value=w.n * steps / el,
+        ms_per_step=1e3 * el / steps,
+        ms_phase=ms_phase,
+        rechecks_per_step=(s1["rechecks"] - s0["rechecks"]) / steps,
+        fallbacks=s1["fallbacks"] - s0["fallbacks"],
+        history=[(int(a), int(b)) for a, b in zip(hn, hd)],
+        pair_tests=pair_tests,
+    )
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, search {ms_phase['search']:.3f} ms")
+    return out
+
+
+def cpu_baseline(n_sample):
+    from oracle import oracle as O
+    from paper_1310_3437_amd import inputs
+    log(f"[bench] cpu baseline: oracle step on the c3_sphere recipe at N={n_sample}")
+    w = inputs.c3_sphere(n=n_sample, steps=1)
+    r = O.Run(w)
+    nt = O.lib().orc_max_threads()
+    t0 = time.perf_counter()
+    r.step()
+    el = time.perf_counter() - t0
+    return dict(value=n_sample / el, unit="particle-steps/s", cores=int(nt), kind="oracle",
+                sample=f"one oracle step (search with {nt} OpenMP threads, serial bin/resolve/stream) "
+                       f"of the c3_sphere recipe at N={n_sample:.0e} (same density law, ~3 particles "
+                       f"per cell), {el:.1f} s; {r.pair_tests / el:.3e} pair-tests/s",
+                pair_tests_per_s=r.pair_tests / el, seconds=el,
+                cpu=platform.processor() or platform.machine())
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=float, default=1e8)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=float, default=1e7)
+    ap.add_argument("--paths", default="fp64,fp32")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1310_3437_amd import inputs, kmc
+    kmc.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    n = int(args.n)
+    t0 = time.perf_counter()
+    w = inputs.c3_sphere(n=n)
+    log(f"[bench] generated c3_sphere N={n} in {time.perf_counter() - t0:.1f} s; "
+        f"cells {w.boxes[0].ncell}, dt {w.boxes[0].dt:.4e}")
+
+    results = {}
+    pair_tests = None
+    have_f32 = "fp32" in args.paths and os.environ.get("KMC_BENCH_NO_F32") is None
+    for name in args.paths.split(","):
+        prec = kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
+        if name == "fp32" and not have_f32:
+            continue
+        r = run_path(kmc, w, prec, args.steps, args.warmup, pair_tests)
+        pair_tests = r["pair_tests"]
+        results[name] = r
+
+    identical = None
+    if "fp64" in results and "fp32" in results:
+        identical = results["fp64"]["history"] == results["fp32"]["history"]
+    head = results.get("fp32") or results["fp64"]
+    head_name = "fp32_screen" if "fp32" in results else "fp64"
+    search_ms = head["ms_phase"]["search"] + head["ms_phase"]["recheck"]
+    flops = FLOP_PER_PAIR_TEST * head["pair_tests"]
+    achieved = flops / (search_ms * 1e-3) / 1e12
+    traffic = traffic_for(head_name, None)
+    line = {
+        "metric": METRIC,
+        "value": head["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head_name == "fp32_screen" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c3_sphere: N={n:.0e} uniform ball R=1, v=-0.5x+N(0,0.1^2), reflecting sphere, "
+                        f"{w.boxes[0].ncell[0]}^3 cells (edge {w.boxes[0].h[0]:.5f} >= D={w.info['D']:.5f}), "
+                        f"dt={w.boxes[0].dt:.4e}",
+            "N": n,
+            "path": head_name,
+        },
+        "roofline": {
+            "kernel": "partner search" + (" (FP32 screen + FP64 recheck)" if head_name == "fp32_screen" else " (FP64)"),
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_VALU_TFLOPS,
+            "traffic": traffic,
+            "flop_per_pair_test": FLOP_PER_PAIR_TEST,
+            "pair_tests_per_launch": head["pair_tests"],
+            "avg_launch_ms": search_ms,
+        },
+        "pair_tests_per_s": head["pair_tests"] * head["value"] / n,
+        "identical_pair_lists": identical,
+        "paths": {k: {kk: vv for kk, vv in v.items() if kk != "history"} for k, v in results.items()},
+    }
+    if "fp64" in results and "fp32" in results:
+        line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

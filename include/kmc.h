@@ -104,7 +104,10 @@ typedef struct kmc_config {
     int32_t use_graph;         /* 1: each step is replayed from a captured hipGraph      */
     int32_t block_size;        /* threads per block, multiple of 64 in [64, 1024]; 0 = 256 */
     int32_t profile;           /* 1: time every phase with HIP events (disables graphs)  */
-    int32_t reserved[7];       /* must be zero                                           */
+    int32_t reserved[5];       /* must be zero                                           */
+    double guard_scale;        /* FP32 screen: factor applied to the derived rounding-error
+                                  bounds; 0 = 4 (default), >= 1 otherwise.  -1 disables the
+                                  bounds (testing only: the screen is then not exact)     */
 } kmc_config;
 
 /* Phases timed in profile mode (indices into kmc_stats.ms). */

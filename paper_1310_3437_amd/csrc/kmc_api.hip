@@ -3,6 +3,7 @@
 // Parameter validation, workspace layout, kernel launch plan, optional
 // hipGraph capture of one step, read-back, statistics.  The library never
 // allocates device memory: everything lives in the caller's workspace.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -66,6 +67,8 @@ int check_cfg(const kmc_config& c)
     if (c.block_size != 0 && (c.block_size < 64 || c.block_size > 1024 || c.block_size % 64 != 0)) return KMC_EINVAL;
     if (c.use_graph != 0 && c.use_graph != 1) return KMC_EINVAL;
     if (c.profile != 0 && c.profile != 1) return KMC_EINVAL;
+    if (!std::isfinite(c.guard_scale) || (c.guard_scale != 0.0 && c.guard_scale != -1.0 && c.guard_scale < 1.0))
+        return KMC_EINVAL;
     for (int r : c.reserved)
         if (r != 0) return KMC_EINVAL;
     return KMC_OK;
@@ -119,8 +122,11 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.hist_np = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
     p.hist_dig = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
     p.A = (double*)take(sizeof(double) * 6 * N);
-    p.B = (double*)take(sizeof(double) * 6 * N);
-    p.B32 = f32 ? (float*)take(sizeof(float) * 6 * N) : nullptr;
+    p.B = (P64*)take(sizeof(P64) * N);
+    p.B32a = f32 ? (float4*)take(sizeof(float4) * N) : nullptr;
+    p.B32b = f32 ? (float2*)take(sizeof(float2) * N) : nullptr;
+    p.box_vmax = (unsigned int*)take(sizeof(unsigned int) * nboxes);
+    p.box_step = (BoxStep*)take(sizeof(BoxStep) * nboxes);
     p.idA = (uint32_t*)take(4 * N);
     p.idB = (uint32_t*)take(4 * N);
     p.cell = (uint32_t*)take(4 * N);
@@ -141,6 +147,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.precision = cfg.precision;
     p.kinematics = cfg.kinematics;
     p.block = cfg.block_size ? cfg.block_size : 256;
+    p.guard = cfg.guard_scale > 0.0 ? (float)cfg.guard_scale : (cfg.guard_scale < 0.0 ? 0.0f : 4.0f);
     return off;
 }
 
@@ -156,6 +163,18 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
         d.periodic[k] = b.bc[k] == KMC_BC_PERIODIC ? 1 : 0;
         d.ctr32[k] = (float)(0.5 * (b.lo[k] + b.hi[k]));
         d.L32[k] = (float)d.L[k];
+    }
+    // Screen input bounds.  Positions lie in [lo, hi]; the FP32 copy holds
+    // fl32(x - ctr) with |x - ctr| <= P.  For a neighbour pair |r_k| <= 2 h_k
+    // (plus rounding of the cell index); r_hat = fl(fl(xj_hat - xi_hat) + s_hat)
+    // errs by at most u (2 P + 2 |r| + 2 L) (periodic) or u (2 P + 2 |r|).
+    const double u = 0x1.0p-24;
+    for (int k = 0; k < 3; ++k) {
+        const double h = d.L[k] / (double)b.ncell[k];
+        d.rmax[k] = 2.0 * h * (1.0 + 1e-9);
+        const double P = std::max(std::fabs(b.lo[k] - (double)d.ctr32[k]), std::fabs(b.hi[k] - (double)d.ctr32[k])) * (1.0 + 1e-9);
+        const double per = d.periodic[k] ? 2.0 * d.L[k] : 0.0;
+        d.er[k] = (float)(u * (2.0 * P + 2.0 * d.rmax[k] + per) * (1.0 + 1e-5));
     }
     d.D2 = b.D2;
     d.dt = b.dt;

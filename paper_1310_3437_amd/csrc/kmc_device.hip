@@ -312,6 +312,7 @@ __global__ __launch_bounds__(1024) void k_scan_partials(Plan p)
         p.ctl->overflow = 0;
         p.ctl->work_next = 0;
     }
+    for (uint32_t b = threadIdx.x; b < p.nboxes; b += blockDim.x) p.box_vmax[b] = 0u;
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
@@ -341,49 +342,146 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
 }
 
 // --------------------------------------------------------------------------
-// a3: cell-sorted copy of the state (and, for the FP32 screen, an FP32 copy
-// of positions relative to the box origin ctr32 and of velocities).
+// a3: cell-sorted copy of the state as 48-byte records; for the FP32 screen
+// also an FP32 copy (positions relative to the box centre, velocities) and
+// the per-box bound on |v_k| that the screen's error bounds need.
 // --------------------------------------------------------------------------
 
 template <bool F32>
 __global__ void k_scatter(Plan p)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.N) return;
+    const bool valid = i < p.N;
     const size_t N = p.N;
-    const uint32_t d = p.start[p.cell[i]] + p.slot[i];
-    double s[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        s[k] = p.A[k * N + i];
-        p.B[k * N + d] = s[k];
+    float vm = 0.f;
+    uint32_t bidx = 0;
+    if (valid) {
+        const uint32_t d = p.start[p.cell[i]] + p.slot[i];
+        P64 r;
+        r.x = p.A[i];
+        r.y = p.A[N + i];
+        r.z = p.A[2 * N + i];
+        r.vx = p.A[3 * N + i];
+        r.vy = p.A[4 * N + i];
+        r.vz = p.A[5 * N + i];
+        p.B[d] = r;
+        p.idB[d] = p.idA[i];
+        if (F32) {
+            bidx = p.boxidx ? p.boxidx[i] : 0u;
+            const BoxDev& B = p.boxes[bidx];
+            float4 a;
+            a.x = (float)(r.x - (double)B.ctr32[0]);
+            a.y = (float)(r.y - (double)B.ctr32[1]);
+            a.z = (float)(r.z - (double)B.ctr32[2]);
+            a.w = (float)r.vx;
+            float2 b;
+            b.x = (float)r.vy;
+            b.y = (float)r.vz;
+            p.B32a[d] = a;
+            p.B32b[d] = b;
+            vm = fmaxf(fabsf(a.w), fmaxf(fabsf(b.x), fabsf(b.y)));
+        }
     }
-    p.idB[d] = p.idA[i];
     if (F32) {
-        const BoxDev& B = box_of(p, i);
+        // per-box maximum: one atomic per wave when the wave lies in one box
+        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)bidx);
+        if (!valid) bidx = b0;
+        if (__all(bidx == b0)) {
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p.B32[k * N + d] = (float)(s[k] - (double)B.ctr32[k]);
-#pragma unroll
-        for (int k = 3; k < 6; ++k) p.B32[k * N + d] = (float)s[k];
+            for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off, 64));
+            if ((threadIdx.x & 63) == 0) atomicMax(&p.box_vmax[b0], __float_as_uint(vm));
+        } else if (valid) {
+            atomicMax(&p.box_vmax[bidx], __float_as_uint(vm));
+        }
     }
 }
 
+// Loose screen thresholds of every box for this step (FP64 arithmetic,
+// rounded up).  They bound, over every neighbour pair of the box, the
+// difference between the FP32 screen's b, -b - dt g2, c2 - D2 g2 and the
+// FP64 definition's, from worst-case magnitudes |r_k| <= 2 h_k and
+// |v_k| <= V (standard forward error analysis of sums and products,
+// Higham 2002, ch. 3), times the guard factor.
+__global__ void k_box_bounds(Plan p)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.nboxes) return;
+    const BoxDev& B = p.boxes[b];
+    const double u = 0x1.0p-24, u64 = 0x1.0p-53;
+    const double g3 = 3.0 * u / (1.0 - 3.0 * u) + 3.0 * u64 / (1.0 - 3.0 * u64);
+    const double g2 = 2.0 * u / (1.0 - 2.0 * u) + 2.0 * u64 / (1.0 - 2.0 * u64);
+    const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * u);
+    const double eg = 4.0001 * u * V;
+    const double G = 2.0 * V;
+    double R[3], er[3];
+    for (int k = 0; k < 3; ++k) { R[k] = B.rmax[k]; er[k] = (double)B.er[k]; }
+    double Eb = 0, Eg2 = 0, Ec2 = 0, sb = 0, sg = 0, sc = 0;
+    for (int k = 0; k < 3; ++k) {
+        Eb += R[k] * eg + G * er[k] + er[k] * eg;
+        sb += (R[k] + er[k]) * (G + eg);
+        Eg2 += 2.0 * G * eg + eg * eg;
+        sg += (G + eg) * (G + eg);
+    }
+    Eb += g3 * sb;
+    Eg2 += g3 * sg;
+    for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+        const double C = R[k1] * G + R[k2] * G;
+        const double Ec = (R[k1] * eg + G * er[k1] + er[k1] * eg) + (R[k2] * eg + G * er[k2] + er[k2] * eg) +
+                          g2 * ((R[k1] + er[k1]) * (G + eg) + (R[k2] + er[k2]) * (G + eg));
+        Ec2 += 2.0 * C * Ec + Ec * Ec;
+        sc += (C + Ec) * (C + Ec);
+    }
+    Ec2 += g3 * sc;
+    const double G2max = 3.0 * (G + eg) * (G + eg);
+    const double Et = Eb + B.dt * (1.0 + u) * Eg2 + 3.0 * u * B.dt * G2max;
+    const double Ecc = Ec2 + B.D2 * (1.0 + u) * Eg2 + 3.0 * u * B.D2 * G2max;
+    const double f = (double)p.guard * (1.0 + 1e-5);
+    BoxStep st;
+    st.Tb = (float)(f * Eb);
+    st.Tt = (float)(f * Et);
+    st.Tc = (float)(f * Ecc);
+    st.vmax = (float)V;
+    p.box_step[b] = st;
+}
+
 // --------------------------------------------------------------------------
-// a4: DCA partner search in FP64, one thread per cell-sorted particle.
+// a4: DCA partner search.
+//
+// One wave (= one block of 64 threads) takes 64 consecutive cell-sorted
+// particles, one per lane.  Lanes whose particles share a cell row (same
+// box, y and z cell) form a group; for each of the nine neighbour rows the
+// group's window of cells cx_first-1 .. cx_last+1 is a contiguous range of
+// the sorted arrays, which the wave stages into LDS (in chunks) with
+// coalesced loads.  Each lane then tests the candidates of its own three
+// cells from LDS.  The inner loop only records acceptable (FP64) or not
+// provably rejectable (FP32) candidates in a few registers; keys, argmin and
+// the FP32 classification run once per particle afterwards.
 // --------------------------------------------------------------------------
 
-// Search of one particle over its 27-cell neighbourhood.  Returns the
-// sorted index of the closest acceptable partner ((key, id) minimum) or -1.
-__device__ __forceinline__ int32_t search_one64(const Plan& p, uint32_t i)
+constexpr int kSlots = 8;
+
+struct Slots {
+    uint32_t s[kSlots];
+    int cnt;
+    __device__ __forceinline__ void add(uint32_t j)
+    {
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) s[k] = (cnt == k) ? j : s[k];
+        ++cnt;
+    }
+};
+
+// Exact FP64 search of one particle straight from the sorted records
+// (used for rechecks, slot overflow and the screen's fallback).
+__device__ int32_t search_one64(const Plan& p, uint32_t i)
 {
     const BoxDev& B = box_of(p, i);
-    const size_t N = p.N;
-    const double* __restrict__ X = p.B;
-    const double xi = X[i], yi = X[N + i], zi = X[2 * N + i];
-    const double ui = X[3 * N + i], vi = X[4 * N + i], wi = X[5 * N + i];
-    const int cx = cell1(xi, B.lo[0], B.inv_h[0], B.nc[0]);
-    const int cy = cell1(yi, B.lo[1], B.inv_h[1], B.nc[1]);
-    const int cz = cell1(zi, B.lo[2], B.inv_h[2], B.nc[2]);
+    const P64* __restrict__ X = p.B;
+    const P64 me = X[i];
+    const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
+    const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
+    const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
     const double D2 = B.D2, dt = B.dt;
     double best_key = __builtin_inf();
     uint32_t best_id = 0xFFFFFFFFu;
@@ -392,17 +490,12 @@ __device__ __forceinline__ int32_t search_one64(const Plan& p, uint32_t i)
         const bool shift = (wx | wy | wz) != 0;
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         for (uint32_t j = s; j < e; ++j) {
-            if (j == i) continue;
-            double rx = X[j] - xi, ry = X[N + j] - yi, rz = X[2 * N + j] - zi;
-            if (shift) {
-                // the image shift is added only where the range wrapped;
-                // adding +0.0 elsewhere changes at most the sign of a zero
-                rx = rx + sx; ry = ry + sy; rz = rz + sz;
-            }
-            const double gx = X[3 * N + j] - ui, gy = X[4 * N + j] - vi, gz = X[5 * N + j] - wi;
-            const PairQ q = pair_q(rx, ry, rz, gx, gy, gz);
-            if (accept(q, D2, dt)) {
-                const double key = q.c2 / q.g2;
+            const P64 q = X[j];
+            double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
+            if (shift) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            if (accept(pq, D2, dt)) {   // the particle itself has g2 = 0 and is never accepted
+                const double key = pq.c2 / pq.g2;
                 const uint32_t idj = p.idB[j];
                 if (key < best_key || (key == best_key && idj < best_id)) {
                     best_key = key;
@@ -415,11 +508,361 @@ __device__ __forceinline__ int32_t search_one64(const Plan& p, uint32_t i)
     return best;
 }
 
-__global__ void k_search64(Plan p)
+// Relative position of candidate j seen from i in FP64 with the image fixed
+// by the two cells, exactly as in the search.
+__device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64& q, double r[3])
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.N) return;
-    p.partner[i] = search_one64(p, i);
+    const double xi[3] = {me.x, me.y, me.z}, xj[3] = {q.x, q.y, q.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int ci = cell1(xi[k], B.lo[k], B.inv_h[k], B.nc[k]);
+        const int cj = cell1(xj[k], B.lo[k], B.inv_h[k], B.nc[k]);
+        const int w = wrap_of(ci, cj, B.nc[k], B.periodic[k]);
+        r[k] = xj[k] - xi[k];
+        if (w != 0) r[k] = r[k] + (double)w * B.L[k];
+    }
+}
+
+struct PolF64 {
+    static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
+    struct Lds {
+        P64 rec[W];
+    };
+    struct Own {
+        P64 me;
+        float pad_;
+    };
+    __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
+    {
+        o.me = p.B[i];
+        x = o.me.x; y = o.me.y; z = o.me.z;
+    }
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j) { l.rec[t] = p.B[j]; }
+    template <bool SH>
+    __device__ static void scan(const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t /*i*/,
+                                const Own& o, const BoxDev& B, const BoxStep& /*st*/,
+                                int wx, int wy, int wz, Slots& sl)
+    {
+        const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
+        const double D2 = B.D2, dt = B.dt;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const P64 q = l.rec[j - c0];
+            double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
+            if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
+            if (accept(pq, D2, dt)) sl.add(j);
+        }
+    }
+    // Closest acceptable partner from the recorded candidates (exact keys).
+    __device__ static void finish(const Plan& p, uint32_t i, bool valid, const Own& o, const BoxDev& B,
+                                  const Slots& sl)
+    {
+        if (!valid) return;
+        int32_t best = -1;
+        if (sl.cnt == 1) {
+            best = (int32_t)sl.s[0];
+        } else if (sl.cnt > 1 && sl.cnt <= kSlots) {
+            double best_key = __builtin_inf();
+            uint32_t best_id = 0xFFFFFFFFu;
+#pragma unroll
+            for (int k = 0; k < kSlots; ++k) {
+                if (k < sl.cnt) {
+                    const uint32_t j = sl.s[k];
+                    const P64 q = p.B[j];
+                    double r[3];
+                    rel64(B, o.me, q, r);
+                    const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
+                    const double key = pq.c2 / pq.g2;
+                    const uint32_t idj = p.idB[j];
+                    if (key < best_key || (key == best_key && idj < best_id)) {
+                        best_key = key;
+                        best_id = idj;
+                        best = (int32_t)j;
+                    }
+                }
+            }
+        } else if (sl.cnt > kSlots) {
+            best = search_one64(p, i);
+        }
+        p.partner[i] = best;
+    }
+};
+
+// FP32 screen.  Candidates are rejected only when the FP64 definition is
+// certain to reject them; everything else is recorded and classified once
+// more with per-pair error bounds into accepted / rejected / undecided.  A
+// particle whose closest partner is not certain goes to the FP64 recheck.
+struct PolF32 {
+    static constexpr int W = 192;         // staged records per chunk (4.5 KiB)
+    struct Lds {
+        float4 a[W];
+        float2 b[W];
+    };
+    struct Own {
+        float x, y, z, vx, vy, vz;
+        double X, Y, Z;
+    };
+    __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
+    {
+        const float4 a = p.B32a[i];
+        const float2 b = p.B32b[i];
+        o.x = a.x; o.y = a.y; o.z = a.z; o.vx = a.w; o.vy = b.x; o.vz = b.y;
+        const P64 m = p.B[i];
+        o.X = m.x; o.Y = m.y; o.Z = m.z;
+        x = m.x; y = m.y; z = m.z;
+    }
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j)
+    {
+        l.a[t] = p.B32a[j];
+        l.b[t] = p.B32b[j];
+    }
+    template <bool SH>
+    __device__ static void scan(const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
+                                const Own& o, const BoxDev& B, const BoxStep& st,
+                                int wx, int wy, int wz, Slots& sl)
+    {
+        const float sx = (float)wx * B.L32[0], sy = (float)wy * B.L32[1], sz = (float)wz * B.L32[2];
+        const float D2 = B.D2_32, dt = B.dt_32;
+        const float Tb = st.Tb, Tt = st.Tt, Tc = st.Tc;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const float4 qa = l.a[j - c0];
+            const float2 qb = l.b[j - c0];
+            float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
+            if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
+            const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
+            const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+            const float cx = fmaf(ry, gz, -(rz * gy));
+            const float cy = fmaf(rz, gx, -(rx * gz));
+            const float cz = fmaf(rx, gy, -(ry * gx));
+            const float c2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+            const float m2 = fmaf(-dt, g2, -b);
+            const float m3 = fmaf(-D2, g2, c2);
+            const bool keep = (b <= Tb) & (m2 <= Tt) & (m3 <= Tc) & (j != i);
+            if (keep) sl.add(j);
+        }
+    }
+    __device__ static void finish(const Plan& p, uint32_t i, bool valid, const Own& o, const BoxDev& B,
+                                  const Slots& sl)
+    {
+        bool need = false;
+        int32_t best = -1;
+        if (valid) {
+            if (sl.cnt > kSlots) {
+                need = true;
+            } else {
+                const float u = 0x1.0p-24f;
+                const float g3 = 3.0f * u * 1.001f + 4e-16f;
+                const float g2c = 2.0f * u * 1.001f + 3e-16f;
+                const float gf = p.guard * 1.001f;
+                float lo1 = __builtin_inff(), hi1 = __builtin_inff(), lo2 = __builtin_inff();
+                int st1 = 0;                       // 0 none, 1 accepted, 2 undecided
+                uint32_t j1 = 0;
+                const double xi[3] = {o.X, o.Y, o.Z};
+                const float pi[3] = {o.x, o.y, o.z}, vi[3] = {o.vx, o.vy, o.vz};
+#pragma unroll
+                for (int k = 0; k < kSlots; ++k) {
+                    if (k < sl.cnt) {
+                        const uint32_t j = sl.s[k];
+                        const float4 qa = p.B32a[j];
+                        const float2 qb = p.B32b[j];
+                        const P64 qj = p.B[j];
+                        const double xj[3] = {qj.x, qj.y, qj.z};
+                        const float pj[3] = {qa.x, qa.y, qa.z}, vj[3] = {qa.w, qb.x, qb.y};
+                        float r[3], g[3], ar[3], ag[3], eg[3], er[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const int ci = cell1(xi[a], B.lo[a], B.inv_h[a], B.nc[a]);
+                            const int cj = cell1(xj[a], B.lo[a], B.inv_h[a], B.nc[a]);
+                            const int w = wrap_of(ci, cj, B.nc[a], B.periodic[a]);
+                            r[a] = pj[a] - pi[a];
+                            if (w != 0) r[a] = r[a] + (float)w * B.L32[a];
+                            g[a] = vj[a] - vi[a];
+                            er[a] = B.er[a];
+                            eg[a] = u * 1.0001f * (fabsf(vi[a]) + fabsf(vj[a]) + fabsf(g[a]));
+                            ar[a] = fabsf(r[a]) + er[a];
+                            ag[a] = fabsf(g[a]) + eg[a];
+                        }
+                        const float b = fmaf(r[2], g[2], fmaf(r[1], g[1], r[0] * g[0]));
+                        const float gg = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
+                        float c[3];
+                        c[0] = fmaf(r[1], g[2], -(r[2] * g[1]));
+                        c[1] = fmaf(r[2], g[0], -(r[0] * g[2]));
+                        c[2] = fmaf(r[0], g[1], -(r[1] * g[0]));
+                        const float cc = fmaf(c[2], c[2], fmaf(c[1], c[1], c[0] * c[0]));
+                        const float m2 = fmaf(-B.dt_32, gg, -b);
+                        const float m3 = fmaf(-B.D2_32, gg, cc);
+                        float Eb = 0.f, Eg = 0.f, sb = 0.f, sg = 0.f, Ecc = 0.f, scc = 0.f;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            Eb += ar[a] * eg[a] + ag[a] * er[a];
+                            sb += ar[a] * ag[a];
+                            Eg += 2.0f * ag[a] * eg[a];
+                            sg += ag[a] * ag[a];
+                        }
+                        Eb += g3 * sb;
+                        Eg += g3 * sg;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+                            const float Ec = ar[a1] * eg[a2] + ag[a2] * er[a1] + ar[a2] * eg[a1] + ag[a1] * er[a2] +
+                                             g2c * (ar[a1] * ag[a2] + ar[a2] * ag[a1]);
+                            const float ac = fabsf(c[a]) + Ec;
+                            Ecc += 2.0f * ac * Ec;
+                            scc += ac * ac;
+                        }
+                        Ecc += g3 * scc;
+                        Eb *= gf;
+                        Eg *= gf;
+                        Ecc *= gf;
+                        const float Et = Eb + B.dt_32 * (1.0f + 2.0f * u) * Eg +
+                                         gf * (3.0f * u * B.dt_32 * (gg + Eg) + 2.0f * u * fabsf(m2));
+                        const float Ec3 = Ecc + B.D2_32 * (1.0f + 2.0f * u) * Eg +
+                                          gf * (3.0f * u * B.D2_32 * (gg + Eg) + 2.0f * u * fabsf(m3));
+                        const bool rej = (b > Eb) | (m2 > Et) | (m3 > Ec3);
+                        if (rej) continue;
+                        const bool acc = (b < -Eb) & (m2 < -Et) & (m3 < -Ec3) & (gg > Eg);
+                        const float kl = fmaxf(cc - Ecc, 0.0f) / (gg + Eg) * (1.0f - 4.0f * u);
+                        const float kh = gg > Eg ? (cc + Ecc) / (gg - Eg) * (1.0f + 4.0f * u) : __builtin_inff();
+                        if (kl < lo1) {
+                            lo2 = lo1;
+                            lo1 = kl;
+                            hi1 = kh;
+                            st1 = acc ? 1 : 2;
+                            j1 = j;
+                        } else if (kl < lo2) {
+                            lo2 = kl;
+                        }
+                    }
+                }
+                if (st1 == 0) best = -1;
+                else if (st1 == 1 && hi1 < lo2) best = (int32_t)j1;
+                else need = true;
+            }
+        }
+        // undecided particles: wave-aggregated append to the recheck list
+        const uint64_t mask = __ballot(need);
+        if (mask) {
+            const int lane = threadIdx.x & 63;
+            const int leader = __ffsll((unsigned long long)mask) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&p.ctl->recheck_count, (unsigned int)__popcll(mask));
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+            if (need) {
+                const uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+                if (idx < p.recheck_cap) p.recheck[idx] = i;
+                else atomicOr(&p.ctl->overflow, 1u);
+            }
+        }
+        if (valid) p.partner[i] = need ? -1 : best;
+    }
+};
+
+template <class Pol>
+__global__ __launch_bounds__(64) void k_search_wave(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    const int lane = threadIdx.x;
+    const uint32_t i = blockIdx.x * 64u + (uint32_t)lane;
+    const bool valid = i < p.N;
+    uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
+    int cx = 0, cy = 0, cz = 0;
+    typename Pol::Own own;
+    if (valid) {
+        bidx = p.boxidx ? p.boxidx[i] : 0u;
+        const BoxDev& B = p.boxes[bidx];
+        double x, y, z;
+        Pol::load_own(p, i, own, x, y, z);
+        cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
+        cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
+        cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
+        rowkey = B.coff + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+    }
+    Slots sl;
+    sl.cnt = 0;
+#pragma unroll
+    for (int k = 0; k < kSlots; ++k) sl.s[k] = 0;
+    uint64_t remaining = __ballot(valid);
+    while (remaining) {
+        const int lead = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
+        const uint64_t grp = __ballot(valid && rowkey == key) & remaining;
+        remaining &= ~grp;
+        const bool in = (grp >> lane) & 1ull;
+        const int last = 63 - __clzll((long long)grp);
+        const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
+        const BoxDev& B = p.boxes[gb];
+        const BoxStep st = p.box_step ? p.box_step[gb] : BoxStep{};
+        const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
+        const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
+        const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
+        // one part = cells [ca, cb] of row `row` seen with image shift (wx, wy, wz);
+        // `mine` tells whether this lane's stencil uses the part and which sub-range
+        auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
+            const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];
+            const bool sh = (wx | wy | wz) != 0;
+            for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
+                const uint32_t n = min((uint32_t)Pol::W, ge - c0);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t);
+                __syncthreads();
+                const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
+                if (sh) Pol::template scan<true>(lds, c0, j0, j1, i, own, B, st, wx, wy, wz, sl);
+                else Pol::template scan<false>(lds, c0, j0, j1, i, own, B, st, wx, wy, wz, sl);
+                __syncthreads();
+            }
+        };
+        for (int dz = -1; dz <= 1; ++dz) {
+            int nz = gcz + dz, wz = 0;
+            if (nz < 0) { if (!B.periodic[2]) continue; nz += NZ; wz = -1; }
+            else if (nz >= NZ) { if (!B.periodic[2]) continue; nz -= NZ; wz = 1; }
+            for (int dy = -1; dy <= 1; ++dy) {
+                int ny = gcy + dy, wy = 0;
+                if (ny < 0) { if (!B.periodic[1]) continue; ny += NY; wy = -1; }
+                else if (ny >= NY) { if (!B.periodic[1]) continue; ny -= NY; wy = 1; }
+                const uint32_t row = B.coff + (uint32_t)NX * ((uint32_t)ny + (uint32_t)NY * (uint32_t)nz);
+                {
+                    uint32_t ls = 0, le = 0;
+                    if (in) {
+                        ls = p.start[row + (cx - 1 < 0 ? 0 : cx - 1)];
+                        le = p.start[row + (cx + 1 >= NX ? NX - 1 : cx + 1) + 1];
+                    }
+                    part(row, cxf - 1 < 0 ? 0 : cxf - 1, cxl + 1 >= NX ? NX - 1 : cxl + 1, ls, le, 0, wy, wz);
+                }
+                if (B.periodic[0]) {
+                    if (cxf - 1 < 0) {
+                        const bool use = in && cx == 0;
+                        part(row, NX - 1, NX - 1, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, -1, wy, wz);
+                    }
+                    if (cxl + 1 >= NX) {
+                        const bool use = in && cx == NX - 1;
+                        part(row, 0, 0, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, 1, wy, wz);
+                    }
+                }
+            }
+        }
+    }
+    const BoxDev& Bm = p.boxes[bidx];
+    Pol::finish(p, i, valid, own, Bm, sl);
+}
+
+// FP64 re-search of the particles the screen left undecided.
+__global__ void k_recheck64(Plan p)
+{
+    const uint32_t cnt = p.ctl->recheck_count;
+    const uint32_t n = cnt < p.recheck_cap ? cnt : p.recheck_cap;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint32_t i = p.recheck[k];
+        p.partner[i] = search_one64(p, i);
+    }
+}
+
+// Whole-step FP64 search when the recheck list overflowed (exits at once
+// otherwise).
+__global__ void k_fallback64(Plan p)
+{
+    if (p.ctl->overflow == 0u) return;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.N; i += gridDim.x * blockDim.x)
+        p.partner[i] = search_one64(p, i);
 }
 
 // --------------------------------------------------------------------------
@@ -469,10 +912,8 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
     if (i < p.N) {
         const BoxDev& B = box_of(p, i);
         const size_t N = p.N;
-        const double* __restrict__ X = p.B;
-        double x[3], v[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) { x[k] = X[k * N + i]; v[k] = X[(3 + k) * N + i]; }
+        const P64 me = p.B[i];
+        double x[3] = {me.x, me.y, me.z}, v[3] = {me.vx, me.vy, me.vz};
         const uint32_t id = p.idB[i];
         const int32_t q = p.partner[i];
         const double dt = B.dt;
@@ -480,9 +921,8 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
         if (q >= 0 && p.partner[q] == (int32_t)i) {
             hit = true;
             const uint32_t idq = p.idB[q];
-            double xq[3], vq[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) { xq[k] = X[k * N + q]; vq[k] = X[(3 + k) * N + q]; }
+            const P64 o = p.B[q];
+            const double xq[3] = {o.x, o.y, o.z}, vq[3] = {o.vx, o.vy, o.vz};
             const bool me_a = id < idq;   // a = the member with the smaller id
             const double* xa = me_a ? x : xq;
             const double* va = me_a ? v : vq;
@@ -573,10 +1013,10 @@ __global__ __launch_bounds__(256) void k_count_tests(Plan p, unsigned long long*
     uint64_t t = 0, z = 0;
     if (i < p.N) {
         const BoxDev& B = box_of(p, i);
-        const size_t N = p.N;
-        const int cx = cell1(p.B[i], B.lo[0], B.inv_h[0], B.nc[0]);
-        const int cy = cell1(p.B[N + i], B.lo[1], B.inv_h[1], B.nc[1]);
-        const int cz = cell1(p.B[2 * N + i], B.lo[2], B.inv_h[2], B.nc[2]);
+        const P64 me = p.B[i];
+        const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
+        const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
+        const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
         for_each_range(B, cx, cy, cz, p.start, [&](uint32_t s, uint32_t e, int, int, int) { t += e - s; });
         t -= 1;
     }
@@ -618,8 +1058,18 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         else k_scatter<false><<<gN, b, 0, s>>>(p);
     }
     mark(KMC_PHASE_SEARCH);
-    if (p.N > 0) k_search64<<<gN, b, 0, s>>>(p);
+    const uint32_t gW = blocks_for(p.N, 64);
+    if (p.precision == KMC_FP32_SCREEN) {
+        k_box_bounds<<<blocks_for(p.nboxes, 64), 64, 0, s>>>(p);
+        if (p.N > 0) k_search_wave<PolF32><<<gW, 64, 0, s>>>(p);
+    } else {
+        if (p.N > 0) k_search_wave<PolF64><<<gW, 64, 0, s>>>(p);
+    }
     mark(KMC_PHASE_RECHECK);
+    if (p.precision == KMC_FP32_SCREEN && p.N > 0) {
+        k_recheck64<<<512, 256, 0, s>>>(p);
+        k_fallback64<<<2048, 256, 0, s>>>(p);
+    }
     mark(KMC_PHASE_RESOLVE);
     if (p.N > 0) k_resolve<<<gN, b, 0, s>>>(p);
     k_advance<<<1, 64, 0, s>>>(p);

@@ -27,13 +27,24 @@ struct alignas(16) BoxDev {
     uint32_t coff;       // first global cell of the box
     uint32_t poff;       // first global particle index of the box
     uint32_t n;          // particles in the box
-    // FP32 screen constants (see the screen kernel for their meaning)
-    float ctr32[3];      // origin of the FP32 position copy
+    // FP32 screen constants
+    float ctr32[3];      // origin of the FP32 position copy (box centre)
     float L32[3];        // periodic shift lengths, rounded to FP32
     float D2_32, dt_32;  // thresholds rounded to FP32
-    float eps_r, eps_v;  // absolute input-rounding bounds of positions/velocities
-    float rmax, vmax;    // magnitude bounds used by the error terms
-    float pad_[2];
+    float er[3];         // bound on |r_hat_k - r_k| for any neighbour pair
+    float pad_;
+    double rmax[3];      // bound on |r_k| for any neighbour pair (2 h_k)
+};
+
+// Cell-sorted FP64 particle record (48 bytes, 16-byte aligned).
+struct alignas(16) P64 {
+    double x, y, z, vx, vy, vz;
+};
+
+// Per-box, per-step screen thresholds (computed after the sorted copy).
+struct alignas(16) BoxStep {
+    float Tb, Tt, Tc;    // loose reject thresholds for b, -b - dt g2, c2 - D2 g2
+    float vmax;          // bound on |v_k| over the box this step
 };
 
 // Per-context control block in device memory.
@@ -56,8 +67,11 @@ struct Plan {
     unsigned long long* hist_np;   // [history][kHistLanes]
     unsigned long long* hist_dig;  // [history][kHistLanes]
     double* A;                     // current state, 6*N SoA (previous cell order)
-    double* B;                     // cell-sorted copy of the current state, 6*N
-    float* B32;                    // FP32 screen copy of B (positions, velocities), 6*N
+    P64* B;                        // cell-sorted copy of the current state (records)
+    float4* B32a;                  // FP32 screen copy: (x, y, z) - box centre, vx
+    float2* B32b;                  // FP32 screen copy: vy, vz
+    unsigned int* box_vmax;        // per box: max |v_k| this step (FP32 bits)
+    BoxStep* box_step;             // per box: screen thresholds this step
     uint32_t* idA;
     uint32_t* idB;
     uint32_t* cell;                // per particle in A order: global cell
@@ -73,6 +87,7 @@ struct Plan {
     uint32_t recheck_cap;
     uint64_t seed;
     int32_t precision, kinematics, block;
+    float guard;                   // FP32 screen: scale of the rounding-error bounds (>= 1)
 };
 
 // Kernel launchers (kmc_device.hip).  `ev`, when not null, points to

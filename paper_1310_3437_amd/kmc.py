@@ -51,7 +51,8 @@ class KmcConfig(C.Structure):
         ("use_graph", C.c_int32),
         ("block_size", C.c_int32),
         ("profile", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("reserved", C.c_int32 * 5),
+        ("guard_scale", C.c_double),
     ]
 
 
@@ -136,7 +137,7 @@ def make_boxes(boxes):
 
 
 def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR, history=0,
-                recheck_capacity=0, use_graph=False, block_size=0, profile=False):
+                recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0):
     c = KmcConfig()
     c.seed = int(seed) & ((1 << 64) - 1)
     c.step0 = int(step0)
@@ -147,6 +148,7 @@ def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR
     c.use_graph = 1 if use_graph else 0
     c.block_size = int(block_size)
     c.profile = 1 if profile else 0
+    c.guard_scale = float(guard_scale)
     return c
 
 

@@ -30,8 +30,16 @@ def state_close(a, b, boxes, offsets):
     return worst
 
 
-def run_parity(kmc, w, steps, check_every=1, **cfg):
-    print(f"\n[parity] {w.name} N={w.n} boxes={len(w.boxes)} steps={steps} cfg={cfg}", flush=True)
+PRECISIONS = ["fp64", "fp32"]
+
+
+def _prec(kmc, name):
+    return kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
+
+
+def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
+    print(f"\n[parity] {w.name} N={w.n} boxes={len(w.boxes)} steps={steps} {precision} cfg={cfg}", flush=True)
+    cfg["precision"] = _prec(kmc, precision)
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics, **cfg)
     ref = O.Run(w)
     digests = []
@@ -51,45 +59,55 @@ def run_parity(kmc, w, steps, check_every=1, **cfg):
     rel = state_close(st, ref_st, w.boxes, w.offsets)
     assert rel <= 1e-12, f"state differs by {rel:.3e} relative"
     exact = bool(np.array_equal(st, ref_st))
+    stats = sim.stats()
+    print(f"[parity] ok exact={exact} rechecks={stats['rechecks']} fallbacks={stats['fallbacks']}", flush=True)
     sim.close()
+    run_parity.last_stats = stats
     return digests, exact
 
 
-def test_c1_small_full(kmc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c1_small_full(kmc, precision):
     w = I.c1_small()
-    d, exact = run_parity(kmc, w, w.steps)
+    d, exact = run_parity(kmc, w, w.steps, precision=precision)
     assert exact
     assert sum(n for n, _ in d) > 1000
 
 
-@pytest.mark.parametrize("cfg", [dict(use_graph=True), dict(block_size=64), dict(block_size=1024, use_graph=True)])
+@pytest.mark.parametrize("cfg", [dict(use_graph=True), dict(block_size=64),
+                                 dict(block_size=1024, use_graph=True),
+                                 dict(block_size=512, use_graph=True, precision="fp32")])
 def test_c1_launch_shapes(kmc, cfg):
     w = I.c1_small(steps=6)
     _, exact = run_parity(kmc, w, w.steps, **cfg)
     assert exact
 
 
-def test_c2_shock_scaled(kmc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c2_shock_scaled(kmc, precision):
     w = I.c2_shock(n=40_000, steps=15)
-    _, exact = run_parity(kmc, w, w.steps, check_every=5)
+    _, exact = run_parity(kmc, w, w.steps, check_every=5, precision=precision)
     assert exact
 
 
-def test_c3_sphere_scaled(kmc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c3_sphere_scaled(kmc, precision):
     w = I.c3_sphere(n=150_000, steps=3)
-    _, exact = run_parity(kmc, w, w.steps)
+    _, exact = run_parity(kmc, w, w.steps, precision=precision)
     assert exact
 
 
-def test_c4_batch_scaled(kmc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c4_batch_scaled(kmc, precision):
     w = I.c4_batch(nboxes=12, n_lo=100, n_hi=4000, steps=4)
-    _, exact = run_parity(kmc, w, w.steps, use_graph=True)
+    _, exact = run_parity(kmc, w, w.steps, use_graph=True, precision=precision)
     assert exact
 
 
-def test_c5_blobs_scaled(kmc):
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_c5_blobs_scaled(kmc, precision):
     w = I.c5_blobs(n=60_000, steps=3)
-    _, exact = run_parity(kmc, w, w.steps)
+    _, exact = run_parity(kmc, w, w.steps, precision=precision)
     assert exact
 
 

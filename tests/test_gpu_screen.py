@@ -1,0 +1,132 @@
+"""GPU checks of the FP32 screen on adversarial inputs.
+
+Isolated pairs (and triples) are placed so that the FP64 decision sits within
+2^-18 .. 2^-50 relative of an acceptance boundary: the interaction radius
+(d_min = D), the end of the step (t* = dt), the start of the step (t* = 0),
+and near-equal keys of two candidates.  Variants add a large common velocity
+(cancellation in g = v_j - v_i) and coordinates far from the origin.  The
+screen must reproduce the FP64 oracle exactly; with its error bounds switched
+off (guard -1) it must not, which shows the bounds carry the exactness.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1310_3437_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def adversarial(seed=0, bulk=0.0, origin=0.0, kinds=("radius", "tend", "tzero", "tie")):
+    """Pairs/triples near decision boundaries, one group per cell on a
+    3-spaced lattice of a 30^3 periodic grid (groups never share a
+    neighbourhood)."""
+    rng = np.random.default_rng(seed)
+    nc, L = 30, 1.0
+    h = L / nc
+    D = 0.9 * h
+    dt = 0.01
+    pts = []
+    for a in range(10):
+        for b in range(10):
+            for c in range(10):
+                ctr = origin + (np.array([3 * a + 1, 3 * b + 1, 3 * c + 1]) + 0.5) * h
+                kind = kinds[rng.integers(len(kinds))]
+                gdir = rng.standard_normal(3)
+                gdir /= np.linalg.norm(gdir)
+                perp = np.cross(gdir, rng.standard_normal(3))
+                perp /= np.linalg.norm(perp)
+                gmag = rng.uniform(0.5, 2.0)
+                eps = 2.0 ** -rng.integers(18, 51) * (1 if rng.random() < 0.5 else -1)
+                if kind == "radius":
+                    t0, d = rng.uniform(0.2, 0.8) * dt, D * (1 + eps)
+                elif kind == "tend":
+                    t0, d = dt * (1 + eps), D * rng.uniform(0.1, 0.9)
+                elif kind == "tzero":
+                    t0, d = eps * dt, D * rng.uniform(0.1, 0.9)
+                else:
+                    t0, d = rng.uniform(0.2, 0.8) * dt, D * rng.uniform(0.2, 0.6)
+                g = gdir * gmag
+                r = -g * t0 + perp * d
+                V0 = rng.standard_normal(3) * bulk
+                pts.append((ctr - r / 2, V0 - g / 2))
+                pts.append((ctr + r / 2, V0 + g / 2))
+                if kind == "tie":
+                    # a third particle seeing the first at a near-equal key
+                    perp2 = np.cross(gdir, perp)
+                    r2 = -g * t0 + perp2 * d * (1 + eps)
+                    pts.append((ctr - r / 2 + r2, V0 - g / 2 + g))
+    n = len(pts)
+    s = np.empty((6, n))
+    for k, (x, v) in enumerate(pts):
+        s[0:3, k] = x
+        s[3:6, k] = v
+    lo = origin
+    s[0:3] = lo + np.mod(s[0:3] - lo, L)
+    box = I.Box(n=n, lo=(lo,) * 3, hi=(lo + L,) * 3, ncell=(nc,) * 3, periodic=(True,) * 3, D2=D * D, dt=dt)
+    perm = rng.permutation(n)
+    return I.Workload("adversarial", [box], s[:, perm].copy(), 1)
+
+
+def gpu_vs_oracle(kmc, w, precision, steps=1, **cfg):
+    sim = kmc.Sim(w.boxes, w.state, seed=w.seed, precision=precision, **cfg)
+    ref = O.Run(w)
+    mism = 0
+    for _ in range(steps):
+        sim.step(1)
+        ref.step()
+        mism += int((sim.partners().cpu().numpy() != ref.partner_by_id).sum())
+    stats = sim.stats()
+    same_state = bool(np.array_equal(sim.state().cpu().numpy(), ref.full_state()))
+    sim.close()
+    return mism, same_state, stats
+
+
+@pytest.mark.parametrize("variant", [dict(), dict(bulk=20.0), dict(origin=1000.0), dict(bulk=5.0, origin=-300.0)])
+def test_screen_exact_on_adversarial_pairs(kmc, variant):
+    w = adversarial(seed=11, **variant)
+    print(f"\n[screen] adversarial {variant} N={w.n}", flush=True)
+    ref_acc = 0
+    mism64, st64, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2)
+    assert mism64 == 0 and st64
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2)
+    print(f"[screen] mismatches={mism} rechecks={stats['rechecks']}", flush=True)
+    assert mism == 0 and same
+    assert stats["rechecks"] > 0          # the near-boundary cases reach the FP64 recheck
+    del ref_acc
+
+
+def test_negative_control_without_error_bounds(kmc):
+    """With the error bounds disabled the FP32 screen decides near-boundary
+    pairs from FP32 values alone and must disagree with the oracle."""
+    w = adversarial(seed=12, kinds=("radius", "tend", "tzero"))
+    mism, _, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, guard_scale=-1.0)
+    print(f"\n[screen] guard off: mismatches={mism} rechecks={stats['rechecks']}", flush=True)
+    assert mism > 0
+    mism_on, _, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN)
+    assert mism_on == 0
+
+
+def test_recheck_overflow_falls_back_to_fp64(kmc):
+    w = adversarial(seed=13)
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, recheck_capacity=1, use_graph=True, steps=2)
+    assert mism == 0 and same
+    assert stats["fallbacks"] >= 1
+
+
+@pytest.mark.parametrize("guard", [1.0, 16.0])
+def test_guard_scale_does_not_change_results(kmc, guard):
+    w = I.c1_small(steps=3)
+    mism, same, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=3, guard_scale=guard)
+    assert mism == 0 and same
+
+
+def test_screen_rechecks_are_rare_on_a_gas(kmc):
+    w = I.c3_sphere(n=400_000, steps=2)
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2)
+    assert mism == 0 and same
+    frac = stats["rechecks"] / (2 * w.n)
+    print(f"\n[screen] c3 N=4e5 recheck fraction {frac:.2e}", flush=True)
+    assert frac < 0.01
