@@ -98,8 +98,10 @@ typedef struct kmc_config {
     int32_t precision;         /* kmc_precision                                          */
     int32_t kinematics;        /* kmc_kinematics                                         */
     uint32_t history;          /* per-step (npairs, digest) slots kept; 0 = 1024         */
-    uint32_t recheck_capacity; /* FP32 screen: particles re-searched in FP64 per step
-                                  before the whole step falls back to the FP64 search;
+    uint32_t recheck_capacity; /* particles re-searched in full FP64 per step (the FP32
+                                  screen's undecided ones, and any particle with more
+                                  candidates than the search records) before the whole
+                                  step falls back to the full FP64 search;
                                   0 = all particles (never falls back)                   */
     int32_t use_graph;         /* 1: each step is replayed from a captured hipGraph      */
     int32_t block_size;        /* threads per block, multiple of 64 in [64, 1024]; 0 = 256 */
@@ -125,7 +127,7 @@ typedef struct kmc_stats {
     uint64_t steps;            /* steps run since kmc_init                              */
     uint64_t n_total;          /* particles over all boxes                              */
     uint64_t cells_total;      /* cells over all boxes                                  */
-    uint64_t rechecks;         /* particles re-searched in FP64 (sum over steps)        */
+    uint64_t rechecks;         /* particles re-searched in full FP64 (sum over steps)   */
     uint64_t fallbacks;        /* steps whose recheck list overflowed                   */
     double ms[8];              /* accumulated milliseconds per phase (profile mode)      */
     uint64_t timed_steps;      /* steps that contributed to ms                          */

@@ -116,15 +116,16 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     const uint32_t H = history_len(cfg);
     const uint32_t nblk = (uint32_t)((C + kScanTile - 1) / kScanTile);
     const bool f32 = cfg.precision == KMC_FP32_SCREEN;
-    const uint32_t cap = f32 ? (cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N) : 0u;
+    const uint32_t cap = cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N;
     p.ctl = (Ctl*)take(sizeof(Ctl));
     p.boxes = (BoxDev*)take(sizeof(BoxDev) * nboxes);
     p.hist_np = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
     p.hist_dig = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
     p.A = (double*)take(sizeof(double) * 6 * N);
     p.B = (P64*)take(sizeof(P64) * N);
-    p.B32a = f32 ? (float4*)take(sizeof(float4) * N) : nullptr;
-    p.B32b = f32 ? (float2*)take(sizeof(float2) * N) : nullptr;
+    const uint32_t blk = cfg.block_size ? (uint32_t)cfg.block_size : 256u;
+    const uint32_t nblk_part = (uint32_t)((N + blk - 1) / blk);
+    p.vmax_part = (float*)take(sizeof(float) * (nblk_part ? nblk_part : 1));
     p.box_vmax = (unsigned int*)take(sizeof(unsigned int) * nboxes);
     p.box_step = (BoxStep*)take(sizeof(BoxStep) * nboxes);
     p.idA = (uint32_t*)take(4 * N);
@@ -132,11 +133,14 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.cell = (uint32_t*)take(4 * N);
     p.slot = (uint32_t*)take(4 * N);
     p.partner = (int32_t*)take(4 * N);
+    p.sl_cnt = (uint32_t*)take(4 * N);
+    p.sl_first = (uint32_t*)take(4 * N);
+    p.sl_idx = (uint32_t*)take(4 * N * (kSlots - 1));
     p.boxidx = nboxes > 1 ? (uint32_t*)take(4 * N) : nullptr;
     p.count = (uint32_t*)take(4 * C);
     p.start = (uint32_t*)take(4 * (C + 1));
     p.partial = (uint32_t*)take(4 * (size_t)(nblk ? nblk : 1));
-    p.recheck = f32 ? (uint32_t*)take(4 * (size_t)(cap ? cap : 1)) : nullptr;
+    p.recheck = (uint32_t*)take(4 * (size_t)(cap ? cap : 1));
     p.N = (uint32_t)N;
     p.C = (uint32_t)C;
     p.nboxes = nboxes;
@@ -147,6 +151,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.precision = cfg.precision;
     p.kinematics = cfg.kinematics;
     p.block = cfg.block_size ? cfg.block_size : 256;
+    p.nblk_part = nblk_part;
     p.guard = cfg.guard_scale > 0.0 ? (float)cfg.guard_scale : (cfg.guard_scale < 0.0 ? 0.0f : 4.0f);
     return off;
 }

@@ -190,9 +190,9 @@ __global__ void k_init_particles(Plan p, const double* __restrict__ in)
     }
 }
 
-__global__ void k_fill_u32(uint32_t* __restrict__ a, uint32_t n, uint32_t v)
+__global__ void k_fill_u32(uint32_t* __restrict__ a, size_t n, uint32_t v)
 {
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = v;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) a[i] = v;
 }
 
 __global__ void k_init_ctl(Plan p, unsigned long long step0)
@@ -239,15 +239,35 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
 __global__ void k_bin(Plan p)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.N) return;
-    const BoxDev& B = box_of(p, i);
-    const size_t N = p.N;
-    const int cx = cell1(p.A[i], B.lo[0], B.inv_h[0], B.nc[0]);
-    const int cy = cell1(p.A[N + i], B.lo[1], B.inv_h[1], B.nc[1]);
-    const int cz = cell1(p.A[2 * N + i], B.lo[2], B.inv_h[2], B.nc[2]);
-    const uint32_t c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
-    p.cell[i] = c;
-    p.slot[i] = atomicAdd(&p.count[c], 1u);
+    const bool valid = i < p.N;
+    uint32_t c = 0xFFFFFFFFu;
+    if (valid) {
+        const BoxDev& B = box_of(p, i);
+        const size_t N = p.N;
+        const int cx = cell1(p.A[i], B.lo[0], B.inv_h[0], B.nc[0]);
+        const int cy = cell1(p.A[N + i], B.lo[1], B.inv_h[1], B.nc[1]);
+        const int cz = cell1(p.A[2 * N + i], B.lo[2], B.inv_h[2], B.nc[2]);
+        c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+        p.cell[i] = c;
+    }
+    // The state is still in the previous step's cell order, so neighbouring
+    // lanes mostly share a cell: each run of equal cells takes its slots
+    // with one atomic issued by the run's first lane.
+    const int lane = threadIdx.x & 63;
+    const uint64_t live = __ballot(valid);
+    if (live == 0) return;
+    const uint32_t prev = __shfl_up(c, 1, 64);
+    const bool head = valid && (lane == 0 || prev != c);
+    const uint64_t H = __ballot(head);
+    const uint64_t upto = (2ull << lane) - 1ull;           // lanes 0..lane
+    const int my_head = 63 - __clzll((long long)(H & upto));
+    const uint64_t above = H & ~upto;
+    const int nvalid = __popcll(live);
+    const int next = above ? __ffsll((unsigned long long)above) - 1 : nvalid;
+    uint32_t base = 0;
+    if (head) base = atomicAdd(&p.count[c], (unsigned int)(next - lane));
+    base = (uint32_t)__shfl((int)base, my_head, 64);
+    if (valid) p.slot[i] = base + (uint32_t)(lane - my_head);
 }
 
 // --------------------------------------------------------------------------
@@ -354,7 +374,6 @@ __global__ void k_scatter(Plan p)
     const bool valid = i < p.N;
     const size_t N = p.N;
     float vm = 0.f;
-    uint32_t bidx = 0;
     if (valid) {
         const uint32_t d = p.start[p.cell[i]] + p.slot[i];
         P64 r;
@@ -366,34 +385,46 @@ __global__ void k_scatter(Plan p)
         r.vz = p.A[5 * N + i];
         p.B[d] = r;
         p.idB[d] = p.idA[i];
-        if (F32) {
-            bidx = p.boxidx ? p.boxidx[i] : 0u;
-            const BoxDev& B = p.boxes[bidx];
-            float4 a;
-            a.x = (float)(r.x - (double)B.ctr32[0]);
-            a.y = (float)(r.y - (double)B.ctr32[1]);
-            a.z = (float)(r.z - (double)B.ctr32[2]);
-            a.w = (float)r.vx;
-            float2 b;
-            b.x = (float)r.vy;
-            b.y = (float)r.vz;
-            p.B32a[d] = a;
-            p.B32b[d] = b;
-            vm = fmaxf(fabsf(a.w), fmaxf(fabsf(b.x), fabsf(b.y)));
-        }
+        if (F32) vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
     }
     if (F32) {
-        // per-box maximum: one atomic per wave when the wave lies in one box
-        const uint32_t b0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)bidx);
-        if (!valid) bidx = b0;
-        if (__all(bidx == b0)) {
+        // per-block maximum of |fl32(v_k)|; k_vmax_reduce folds the blocks of each box
+        __shared__ float wmax[16];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off, 64));
-            if ((threadIdx.x & 63) == 0) atomicMax(&p.box_vmax[b0], __float_as_uint(vm));
-        } else if (valid) {
-            atomicMax(&p.box_vmax[bidx], __float_as_uint(vm));
+        for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off, 64));
+        if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = vm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = 0.f;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wmax[w]);
+            p.vmax_part[blockIdx.x] = m;
         }
     }
+}
+
+// Per-box maximum of the scatter blocks' partials: kVmaxSplit blocks per
+// box, one atomic each (non-negative floats order like their bit patterns).
+constexpr uint32_t kVmaxSplit = 32;
+
+__global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
+{
+    __shared__ float red[256];
+    const uint32_t b = blockIdx.x / kVmaxSplit, part = blockIdx.x % kVmaxSplit;
+    const BoxDev& B = p.boxes[b];
+    float vm = 0.f;
+    if (B.n > 0) {
+        const uint32_t blk = (uint32_t)p.block;
+        const uint32_t first = B.poff / blk, last = (B.poff + B.n - 1) / blk;
+        for (uint32_t k = first + part * blockDim.x + threadIdx.x; k <= last; k += kVmaxSplit * blockDim.x)
+            vm = fmaxf(vm, p.vmax_part[k]);
+    }
+    red[threadIdx.x] = vm;
+    __syncthreads();
+    for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && red[0] > 0.f) atomicMax(&p.box_vmax[b], __float_as_uint(red[0]));
 }
 
 // Loose screen thresholds of every box for this step (FP64 arithmetic,
@@ -407,10 +438,11 @@ __global__ void k_box_bounds(Plan p)
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= p.nboxes) return;
     const BoxDev& B = p.boxes[b];
+    const float vm = __uint_as_float(p.box_vmax[b]);
     const double u = 0x1.0p-24, u64 = 0x1.0p-53;
     const double g3 = 3.0 * u / (1.0 - 3.0 * u) + 3.0 * u64 / (1.0 - 3.0 * u64);
     const double g2 = 2.0 * u / (1.0 - 2.0 * u) + 2.0 * u64 / (1.0 - 2.0 * u64);
-    const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * u);
+    const double V = (double)vm * (1.0 + 3.0 * u);
     const double eg = 4.0001 * u * V;
     const double G = 2.0 * V;
     double R[3], er[3];
@@ -448,32 +480,25 @@ __global__ void k_box_bounds(Plan p)
 // --------------------------------------------------------------------------
 // a4: DCA partner search.
 //
+// The pair quantities are symmetric under exchange of the two particles
+// (r, g and r x g change sign, b, g2, c2 do not), so every unordered pair is
+// tested once, from the particle whose cell comes first in a half
+// neighbourhood: its own row from the particle onwards through cell cx+1,
+// the row y+1 (cells cx-1..cx+1) and the three rows z+1 (y-1..y+1).  A pair
+// that passes is recorded in the candidate lists of both particles; a
+// per-particle finish pass then takes the exact FP64 (key, id) minimum, or,
+// for the FP32 screen, classifies the recorded candidates.
+//
 // One wave (= one block of 64 threads) takes 64 consecutive cell-sorted
-// particles, one per lane.  Lanes whose particles share a cell row (same
-// box, y and z cell) form a group; for each of the nine neighbour rows the
-// group's window of cells cx_first-1 .. cx_last+1 is a contiguous range of
-// the sorted arrays, which the wave stages into LDS (in chunks) with
-// coalesced loads.  Each lane then tests the candidates of its own three
-// cells from LDS.  The inner loop only records acceptable (FP64) or not
-// provably rejectable (FP32) candidates in a few registers; keys, argmin and
-// the FP32 classification run once per particle afterwards.
+// particles, one per lane.  Lanes whose particles share a cell row form a
+// group; for each of the five half-neighbourhood rows the group's window of
+// cells is a contiguous range of the sorted arrays, which the wave stages
+// into LDS in chunks with coalesced loads.  Each lane then tests its own
+// sub-range of the window from LDS.
 // --------------------------------------------------------------------------
 
-constexpr int kSlots = 8;
-
-struct Slots {
-    uint32_t s[kSlots];
-    int cnt;
-    __device__ __forceinline__ void add(uint32_t j)
-    {
-#pragma unroll
-        for (int k = 0; k < kSlots; ++k) s[k] = (cnt == k) ? j : s[k];
-        ++cnt;
-    }
-};
-
-// Exact FP64 search of one particle straight from the sorted records
-// (used for rechecks, slot overflow and the screen's fallback).
+// Exact FP64 search of one particle over its full 27-cell neighbourhood,
+// straight from the sorted records (rechecks, list overflow, fallback).
 __device__ int32_t search_one64(const Plan& p, uint32_t i)
 {
     const BoxDev& B = box_of(p, i);
@@ -523,6 +548,56 @@ __device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64&
     }
 }
 
+// Slot k of particle i's candidate list (slot 0 lives in a dense array: most
+// particles have at most one candidate).
+__device__ __forceinline__ uint32_t* slot_ptr(const Plan& p, uint32_t i, uint32_t k)
+{
+    return k == 0 ? p.sl_first + i : p.sl_idx + (size_t)i * (kSlots - 1) + (k - 1);
+}
+
+// Record the unordered pair {i, j} in the candidate lists of both.
+__device__ __forceinline__ void record_pair(const Plan& p, uint32_t i, uint32_t j)
+{
+    uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
+    if (k < (uint32_t)kSlots) *slot_ptr(p, i, k) = j;
+    k = atomicAdd(&p.sl_cnt[j], 1u);
+    if (k < (uint32_t)kSlots) *slot_ptr(p, j, k) = i;
+}
+
+// Pairs a lane found, kept in registers until the end of the wave's search
+// (a global atomic inside the search loop would stall the whole wave); a
+// lane that finds more records the excess at once.
+constexpr int kReg = 4;
+
+struct Found {
+    uint32_t j[kReg];
+    int n;
+    __device__ __forceinline__ void add(const Plan& p, uint32_t i, uint32_t jj)
+    {
+        if (n < kReg) {
+#pragma unroll
+            for (int k = 0; k < kReg; ++k) j[k] = (n == k) ? jj : j[k];
+            ++n;
+        } else {
+            record_pair(p, i, jj);
+        }
+    }
+    // append the kept pairs to both candidate lists
+    __device__ __forceinline__ void flush(const Plan& p, uint32_t i)
+    {
+        if (n == 0) return;
+        const uint32_t base = atomicAdd(&p.sl_cnt[i], (unsigned int)n);
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) {
+            if (k < n) {
+                if (base + k < (uint32_t)kSlots) *slot_ptr(p, i, base + k) = j[k];
+                const uint32_t q = atomicAdd(&p.sl_cnt[j[k]], 1u);
+                if (q < (uint32_t)kSlots) *slot_ptr(p, j[k], q) = i;
+            }
+        }
+    }
+};
+
 struct PolF64 {
     static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
     struct Lds {
@@ -530,18 +605,17 @@ struct PolF64 {
     };
     struct Own {
         P64 me;
-        float pad_;
     };
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         o.me = p.B[i];
         x = o.me.x; y = o.me.y; z = o.me.z;
     }
-    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j) { l.rec[t] = p.B[j]; }
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev&) { l.rec[t] = p.B[j]; }
     template <bool SH>
-    __device__ static void scan(const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t /*i*/,
-                                const Own& o, const BoxDev& B, const BoxStep& /*st*/,
-                                int wx, int wy, int wz, Slots& sl)
+    __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
+                                const Own& o, const BoxDev& B, const BoxStep& /*st*/, int wx, int wy, int wz,
+                                Found& f)
     {
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         const double D2 = B.D2, dt = B.dt;
@@ -550,48 +624,13 @@ struct PolF64 {
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            if (accept(pq, D2, dt)) sl.add(j);
+            if (accept(pq, D2, dt)) f.add(p, i, j);
         }
-    }
-    // Closest acceptable partner from the recorded candidates (exact keys).
-    __device__ static void finish(const Plan& p, uint32_t i, bool valid, const Own& o, const BoxDev& B,
-                                  const Slots& sl)
-    {
-        if (!valid) return;
-        int32_t best = -1;
-        if (sl.cnt == 1) {
-            best = (int32_t)sl.s[0];
-        } else if (sl.cnt > 1 && sl.cnt <= kSlots) {
-            double best_key = __builtin_inf();
-            uint32_t best_id = 0xFFFFFFFFu;
-#pragma unroll
-            for (int k = 0; k < kSlots; ++k) {
-                if (k < sl.cnt) {
-                    const uint32_t j = sl.s[k];
-                    const P64 q = p.B[j];
-                    double r[3];
-                    rel64(B, o.me, q, r);
-                    const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-                    const double key = pq.c2 / pq.g2;
-                    const uint32_t idj = p.idB[j];
-                    if (key < best_key || (key == best_key && idj < best_id)) {
-                        best_key = key;
-                        best_id = idj;
-                        best = (int32_t)j;
-                    }
-                }
-            }
-        } else if (sl.cnt > kSlots) {
-            best = search_one64(p, i);
-        }
-        p.partner[i] = best;
     }
 };
 
-// FP32 screen.  Candidates are rejected only when the FP64 definition is
-// certain to reject them; everything else is recorded and classified once
-// more with per-pair error bounds into accepted / rejected / undecided.  A
-// particle whose closest partner is not certain goes to the FP64 recheck.
+// FP32 screen: a candidate is dropped only when the FP64 definition is
+// certain to reject it (thresholds from the per-box bounds of this step).
 struct PolF32 {
     static constexpr int W = 192;         // staged records per chunk (4.5 KiB)
     struct Lds {
@@ -600,26 +639,31 @@ struct PolF32 {
     };
     struct Own {
         float x, y, z, vx, vy, vz;
-        double X, Y, Z;
     };
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
-        const float4 a = p.B32a[i];
-        const float2 b = p.B32b[i];
-        o.x = a.x; o.y = a.y; o.z = a.z; o.vx = a.w; o.vy = b.x; o.vz = b.y;
         const P64 m = p.B[i];
-        o.X = m.x; o.Y = m.y; o.Z = m.z;
+        const BoxDev& B = box_of(p, i);
+        o.x = (float)(m.x - (double)B.ctr32[0]);
+        o.y = (float)(m.y - (double)B.ctr32[1]);
+        o.z = (float)(m.z - (double)B.ctr32[2]);
+        o.vx = (float)m.vx; o.vy = (float)m.vy; o.vz = (float)m.vz;
         x = m.x; y = m.y; z = m.z;
     }
-    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j)
+    // FP32 screen copy of a record: position relative to the box centre and
+    // velocity, each rounded once to FP32 (the candidates staged belong to the
+    // box of the staging group)
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev& B)
     {
-        l.a[t] = p.B32a[j];
-        l.b[t] = p.B32b[j];
+        const P64 q = p.B[j];
+        l.a[t] = make_float4((float)(q.x - (double)B.ctr32[0]), (float)(q.y - (double)B.ctr32[1]),
+                             (float)(q.z - (double)B.ctr32[2]), (float)q.vx);
+        l.b[t] = make_float2((float)q.vy, (float)q.vz);
     }
     template <bool SH>
-    __device__ static void scan(const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
-                                const Own& o, const BoxDev& B, const BoxStep& st,
-                                int wx, int wy, int wz, Slots& sl)
+    __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
+                                const Own& o, const BoxDev& B, const BoxStep& st, int wx, int wy, int wz,
+                                Found& f)
     {
         const float sx = (float)wx * B.L32[0], sy = (float)wy * B.L32[1], sz = (float)wz * B.L32[2];
         const float D2 = B.D2_32, dt = B.dt_32;
@@ -638,128 +682,18 @@ struct PolF32 {
             const float c2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
             const float m2 = fmaf(-dt, g2, -b);
             const float m3 = fmaf(-D2, g2, c2);
-            const bool keep = (b <= Tb) & (m2 <= Tt) & (m3 <= Tc) & (j != i);
-            if (keep) sl.add(j);
+            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) f.add(p, i, j);
         }
-    }
-    __device__ static void finish(const Plan& p, uint32_t i, bool valid, const Own& o, const BoxDev& B,
-                                  const Slots& sl)
-    {
-        bool need = false;
-        int32_t best = -1;
-        if (valid) {
-            if (sl.cnt > kSlots) {
-                need = true;
-            } else {
-                const float u = 0x1.0p-24f;
-                const float g3 = 3.0f * u * 1.001f + 4e-16f;
-                const float g2c = 2.0f * u * 1.001f + 3e-16f;
-                const float gf = p.guard * 1.001f;
-                float lo1 = __builtin_inff(), hi1 = __builtin_inff(), lo2 = __builtin_inff();
-                int st1 = 0;                       // 0 none, 1 accepted, 2 undecided
-                uint32_t j1 = 0;
-                const double xi[3] = {o.X, o.Y, o.Z};
-                const float pi[3] = {o.x, o.y, o.z}, vi[3] = {o.vx, o.vy, o.vz};
-#pragma unroll
-                for (int k = 0; k < kSlots; ++k) {
-                    if (k < sl.cnt) {
-                        const uint32_t j = sl.s[k];
-                        const float4 qa = p.B32a[j];
-                        const float2 qb = p.B32b[j];
-                        const P64 qj = p.B[j];
-                        const double xj[3] = {qj.x, qj.y, qj.z};
-                        const float pj[3] = {qa.x, qa.y, qa.z}, vj[3] = {qa.w, qb.x, qb.y};
-                        float r[3], g[3], ar[3], ag[3], eg[3], er[3];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const int ci = cell1(xi[a], B.lo[a], B.inv_h[a], B.nc[a]);
-                            const int cj = cell1(xj[a], B.lo[a], B.inv_h[a], B.nc[a]);
-                            const int w = wrap_of(ci, cj, B.nc[a], B.periodic[a]);
-                            r[a] = pj[a] - pi[a];
-                            if (w != 0) r[a] = r[a] + (float)w * B.L32[a];
-                            g[a] = vj[a] - vi[a];
-                            er[a] = B.er[a];
-                            eg[a] = u * 1.0001f * (fabsf(vi[a]) + fabsf(vj[a]) + fabsf(g[a]));
-                            ar[a] = fabsf(r[a]) + er[a];
-                            ag[a] = fabsf(g[a]) + eg[a];
-                        }
-                        const float b = fmaf(r[2], g[2], fmaf(r[1], g[1], r[0] * g[0]));
-                        const float gg = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
-                        float c[3];
-                        c[0] = fmaf(r[1], g[2], -(r[2] * g[1]));
-                        c[1] = fmaf(r[2], g[0], -(r[0] * g[2]));
-                        c[2] = fmaf(r[0], g[1], -(r[1] * g[0]));
-                        const float cc = fmaf(c[2], c[2], fmaf(c[1], c[1], c[0] * c[0]));
-                        const float m2 = fmaf(-B.dt_32, gg, -b);
-                        const float m3 = fmaf(-B.D2_32, gg, cc);
-                        float Eb = 0.f, Eg = 0.f, sb = 0.f, sg = 0.f, Ecc = 0.f, scc = 0.f;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            Eb += ar[a] * eg[a] + ag[a] * er[a];
-                            sb += ar[a] * ag[a];
-                            Eg += 2.0f * ag[a] * eg[a];
-                            sg += ag[a] * ag[a];
-                        }
-                        Eb += g3 * sb;
-                        Eg += g3 * sg;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-                            const float Ec = ar[a1] * eg[a2] + ag[a2] * er[a1] + ar[a2] * eg[a1] + ag[a1] * er[a2] +
-                                             g2c * (ar[a1] * ag[a2] + ar[a2] * ag[a1]);
-                            const float ac = fabsf(c[a]) + Ec;
-                            Ecc += 2.0f * ac * Ec;
-                            scc += ac * ac;
-                        }
-                        Ecc += g3 * scc;
-                        Eb *= gf;
-                        Eg *= gf;
-                        Ecc *= gf;
-                        const float Et = Eb + B.dt_32 * (1.0f + 2.0f * u) * Eg +
-                                         gf * (3.0f * u * B.dt_32 * (gg + Eg) + 2.0f * u * fabsf(m2));
-                        const float Ec3 = Ecc + B.D2_32 * (1.0f + 2.0f * u) * Eg +
-                                          gf * (3.0f * u * B.D2_32 * (gg + Eg) + 2.0f * u * fabsf(m3));
-                        const bool rej = (b > Eb) | (m2 > Et) | (m3 > Ec3);
-                        if (rej) continue;
-                        const bool acc = (b < -Eb) & (m2 < -Et) & (m3 < -Ec3) & (gg > Eg);
-                        const float kl = fmaxf(cc - Ecc, 0.0f) / (gg + Eg) * (1.0f - 4.0f * u);
-                        const float kh = gg > Eg ? (cc + Ecc) / (gg - Eg) * (1.0f + 4.0f * u) : __builtin_inff();
-                        if (kl < lo1) {
-                            lo2 = lo1;
-                            lo1 = kl;
-                            hi1 = kh;
-                            st1 = acc ? 1 : 2;
-                            j1 = j;
-                        } else if (kl < lo2) {
-                            lo2 = kl;
-                        }
-                    }
-                }
-                if (st1 == 0) best = -1;
-                else if (st1 == 1 && hi1 < lo2) best = (int32_t)j1;
-                else need = true;
-            }
-        }
-        // undecided particles: wave-aggregated append to the recheck list
-        const uint64_t mask = __ballot(need);
-        if (mask) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((unsigned long long)mask) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(&p.ctl->recheck_count, (unsigned int)__popcll(mask));
-            base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
-            if (need) {
-                const uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-                if (idx < p.recheck_cap) p.recheck[idx] = i;
-                else atomicOr(&p.ctl->overflow, 1u);
-            }
-        }
-        if (valid) p.partner[i] = need ? -1 : best;
     }
 };
 
+#ifndef KMC_SEARCH_WAVES_PER_EU
+#define KMC_SEARCH_WAVES_PER_EU 5
+#endif
+
 template <class Pol>
-__global__ __launch_bounds__(64) void k_search_wave(Plan p)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KMC_SEARCH_WAVES_PER_EU)))
+void k_search_half(Plan p)
 {
     __shared__ typename Pol::Lds lds;
     const int lane = threadIdx.x;
@@ -778,10 +712,10 @@ __global__ __launch_bounds__(64) void k_search_wave(Plan p)
         cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
         rowkey = B.coff + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
     }
-    Slots sl;
-    sl.cnt = 0;
+    Found found;
+    found.n = 0;
 #pragma unroll
-    for (int k = 0; k < kSlots; ++k) sl.s[k] = 0;
+    for (int k = 0; k < kReg; ++k) found.j[k] = 0;
     uint64_t remaining = __ballot(valid);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
@@ -792,57 +726,232 @@ __global__ __launch_bounds__(64) void k_search_wave(Plan p)
         const int last = 63 - __clzll((long long)grp);
         const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
         const BoxDev& B = p.boxes[gb];
-        const BoxStep st = p.box_step ? p.box_step[gb] : BoxStep{};
+        const BoxStep st = p.box_step[gb];
         const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
         const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
-        // one part = cells [ca, cb] of row `row` seen with image shift (wx, wy, wz);
-        // `mine` tells whether this lane's stencil uses the part and which sub-range
+        // Cells [ca, cb] of a row seen with image shift (wx, wy, wz); each lane
+        // tests the sub-range [ls, le) of it (empty when ls >= le).
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
             const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];
             const bool sh = (wx | wy | wz) != 0;
             for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
                 const uint32_t n = min((uint32_t)Pol::W, ge - c0);
-                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t, B);
                 __syncthreads();
                 const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
-                if (sh) Pol::template scan<true>(lds, c0, j0, j1, i, own, B, st, wx, wy, wz, sl);
-                else Pol::template scan<false>(lds, c0, j0, j1, i, own, B, st, wx, wy, wz, sl);
+                if (sh) Pol::template scan<true>(p, lds, c0, j0, j1, i, own, B, st, wx, wy, wz, found);
+                else Pol::template scan<false>(p, lds, c0, j0, j1, i, own, B, st, wx, wy, wz, found);
                 __syncthreads();
             }
         };
-        for (int dz = -1; dz <= 1; ++dz) {
+        // a wrapped end cell of a periodic x axis, used by lanes at that end
+        auto wrap_cell = [&](uint32_t row, int cell, bool use, int wx, int wy, int wz) {
+            part(row, cell, cell, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, wx, wy, wz);
+        };
+        // own row: the rest of the own cell after i, and cell cx+1
+        {
+            const uint32_t row = key;
+            const int cb = cxl + 1 >= NX ? NX - 1 : cxl + 1;
+            uint32_t ls = 0, le = 0;
+            if (in) {
+                ls = i + 1;
+                le = p.start[row + (cx + 1 >= NX ? NX - 1 : cx + 1) + 1];
+            }
+            part(row, cxf, cb, ls, le, 0, 0, 0);
+            if (B.periodic[0] && cxl + 1 >= NX) wrap_cell(row, 0, in && cx == NX - 1, 1, 0, 0);
+        }
+        // rows (dy, dz) = (+1, 0), (-1, +1), (0, +1), (+1, +1): cells cx-1..cx+1
+        for (int r = 0; r < 4; ++r) {
+            const int dy = r == 0 ? 1 : r - 2, dz = r == 0 ? 0 : 1;
             int nz = gcz + dz, wz = 0;
-            if (nz < 0) { if (!B.periodic[2]) continue; nz += NZ; wz = -1; }
-            else if (nz >= NZ) { if (!B.periodic[2]) continue; nz -= NZ; wz = 1; }
-            for (int dy = -1; dy <= 1; ++dy) {
-                int ny = gcy + dy, wy = 0;
-                if (ny < 0) { if (!B.periodic[1]) continue; ny += NY; wy = -1; }
-                else if (ny >= NY) { if (!B.periodic[1]) continue; ny -= NY; wy = 1; }
-                const uint32_t row = B.coff + (uint32_t)NX * ((uint32_t)ny + (uint32_t)NY * (uint32_t)nz);
-                {
-                    uint32_t ls = 0, le = 0;
-                    if (in) {
-                        ls = p.start[row + (cx - 1 < 0 ? 0 : cx - 1)];
-                        le = p.start[row + (cx + 1 >= NX ? NX - 1 : cx + 1) + 1];
-                    }
-                    part(row, cxf - 1 < 0 ? 0 : cxf - 1, cxl + 1 >= NX ? NX - 1 : cxl + 1, ls, le, 0, wy, wz);
-                }
-                if (B.periodic[0]) {
-                    if (cxf - 1 < 0) {
-                        const bool use = in && cx == 0;
-                        part(row, NX - 1, NX - 1, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, -1, wy, wz);
-                    }
-                    if (cxl + 1 >= NX) {
-                        const bool use = in && cx == NX - 1;
-                        part(row, 0, 0, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, 1, wy, wz);
-                    }
-                }
+            if (nz >= NZ) { if (!B.periodic[2]) continue; nz -= NZ; wz = 1; }
+            int ny = gcy + dy, wy = 0;
+            if (ny < 0) { if (!B.periodic[1]) continue; ny += NY; wy = -1; }
+            else if (ny >= NY) { if (!B.periodic[1]) continue; ny -= NY; wy = 1; }
+            const uint32_t row = B.coff + (uint32_t)NX * ((uint32_t)ny + (uint32_t)NY * (uint32_t)nz);
+            uint32_t ls = 0, le = 0;
+            if (in) {
+                ls = p.start[row + (cx - 1 < 0 ? 0 : cx - 1)];
+                le = p.start[row + (cx + 1 >= NX ? NX - 1 : cx + 1) + 1];
+            }
+            part(row, cxf - 1 < 0 ? 0 : cxf - 1, cxl + 1 >= NX ? NX - 1 : cxl + 1, ls, le, 0, wy, wz);
+            if (B.periodic[0]) {
+                if (cxf - 1 < 0) wrap_cell(row, NX - 1, in && cx == 0, -1, wy, wz);
+                if (cxl + 1 >= NX) wrap_cell(row, 0, in && cx == NX - 1, 1, wy, wz);
             }
         }
     }
-    const BoxDev& Bm = p.boxes[bidx];
-    Pol::finish(p, i, valid, own, Bm, sl);
+    if (valid) found.flush(p, i);
+}
+
+// Wave-aggregated append of this lane's particle to the FP64 recheck list
+// (all lanes of the wave must call it).
+__device__ __forceinline__ void push_recheck(const Plan& p, uint32_t i, bool need)
+{
+    const uint64_t mask = __ballot(need);
+    if (!mask) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&p.ctl->recheck_count, (unsigned int)__popcll(mask));
+    base = (uint32_t)__builtin_amdgcn_readlane((int)base, leader);
+    if (need) {
+        const uint32_t idx = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (idx < p.recheck_cap) p.recheck[idx] = i;
+        else atomicOr(&p.ctl->overflow, 1u);
+    }
+}
+
+// Partner of every particle from its recorded candidates (FP64: all of
+// them are acceptable; the (key, id) minimum is taken with exact keys).
+__global__ __launch_bounds__(256) void k_finish64(Plan p)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < p.N;
+    const uint32_t cnt = valid ? p.sl_cnt[i] : 0u;
+    int32_t best = -1;
+    if (cnt != 0) p.sl_cnt[i] = 0u;
+    if (cnt == 1) {
+        best = (int32_t)p.sl_first[i];
+    } else if (cnt > 1 && cnt <= (uint32_t)kSlots) {
+        const BoxDev& B = box_of(p, i);
+        const P64 me = p.B[i];
+        double best_key = __builtin_inf();
+        uint32_t best_id = 0xFFFFFFFFu;
+        for (uint32_t k = 0; k < cnt; ++k) {
+            const uint32_t j = *slot_ptr(p, i, k);
+            const P64 q = p.B[j];
+            double r[3];
+            rel64(B, me, q, r);
+            const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            const double key = pq.c2 / pq.g2;
+            const uint32_t idj = p.idB[j];
+            if (key < best_key || (key == best_key && idj < best_id)) {
+                best_key = key;
+                best_id = idj;
+                best = (int32_t)j;
+            }
+        }
+    }
+    // more candidates than slots: the particle is searched again in full
+    const bool need = cnt > (uint32_t)kSlots;
+    push_recheck(p, i, need);
+    if (valid) p.partner[i] = best;
+}
+
+// FP32 screen finish: every recorded candidate is classified with per-pair
+// rounding-error bounds (Higham 2002, ch. 3) into certainly rejected,
+// certainly accepted or undecided by the FP64 definition, with an interval
+// that certainly contains its FP64 key.  The partner is certain when the
+// candidate with the lowest key bound is certainly accepted and its upper
+// bound lies below every other candidate's lower bound; otherwise the
+// particle is appended to the FP64 recheck list.
+__global__ __launch_bounds__(256) void k_finish32(Plan p)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < p.N;
+    bool need = false;
+    int32_t best = -1;
+    if (valid) {
+        const uint32_t cnt = p.sl_cnt[i];
+        if (cnt != 0) p.sl_cnt[i] = 0u;
+        if (cnt > (uint32_t)kSlots) {
+            need = true;
+        } else if (cnt > 0) {
+            const BoxDev& B = box_of(p, i);
+            const float u = 0x1.0p-24f;
+            const float g3 = 3.0f * u * 1.001f + 4e-16f;
+            const float g2c = 2.0f * u * 1.001f + 3e-16f;
+            const float gf = p.guard * 1.001f;
+            float lo1 = __builtin_inff(), hi1 = __builtin_inff(), lo2 = __builtin_inff();
+            int st1 = 0;                       // 0 none, 1 accepted, 2 undecided
+            uint32_t j1 = 0;
+            const P64 mi = p.B[i];
+            const double xi[3] = {mi.x, mi.y, mi.z};
+            const float pi[3] = {(float)(mi.x - (double)B.ctr32[0]), (float)(mi.y - (double)B.ctr32[1]),
+                                 (float)(mi.z - (double)B.ctr32[2])};
+            const float vi[3] = {(float)mi.vx, (float)mi.vy, (float)mi.vz};
+            for (uint32_t k = 0; k < cnt; ++k) {
+                const uint32_t j = *slot_ptr(p, i, k);
+                const P64 qj = p.B[j];
+                const double xj[3] = {qj.x, qj.y, qj.z};
+                const float pj[3] = {(float)(qj.x - (double)B.ctr32[0]), (float)(qj.y - (double)B.ctr32[1]),
+                                     (float)(qj.z - (double)B.ctr32[2])};
+                const float vj[3] = {(float)qj.vx, (float)qj.vy, (float)qj.vz};
+                float r[3], g[3], ar[3], ag[3], eg[3], er[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int ci = cell1(xi[a], B.lo[a], B.inv_h[a], B.nc[a]);
+                    const int cj = cell1(xj[a], B.lo[a], B.inv_h[a], B.nc[a]);
+                    const int w = wrap_of(ci, cj, B.nc[a], B.periodic[a]);
+                    r[a] = pj[a] - pi[a];
+                    if (w != 0) r[a] = r[a] + (float)w * B.L32[a];
+                    g[a] = vj[a] - vi[a];
+                    er[a] = B.er[a];
+                    eg[a] = u * 1.0001f * (fabsf(vi[a]) + fabsf(vj[a]) + fabsf(g[a]));
+                    ar[a] = fabsf(r[a]) + er[a];
+                    ag[a] = fabsf(g[a]) + eg[a];
+                }
+                const float b = fmaf(r[2], g[2], fmaf(r[1], g[1], r[0] * g[0]));
+                const float gg = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
+                float c[3];
+                c[0] = fmaf(r[1], g[2], -(r[2] * g[1]));
+                c[1] = fmaf(r[2], g[0], -(r[0] * g[2]));
+                c[2] = fmaf(r[0], g[1], -(r[1] * g[0]));
+                const float cc = fmaf(c[2], c[2], fmaf(c[1], c[1], c[0] * c[0]));
+                const float m2 = fmaf(-B.dt_32, gg, -b);
+                const float m3 = fmaf(-B.D2_32, gg, cc);
+                float Eb = 0.f, Eg = 0.f, sb = 0.f, sg = 0.f, Ecc = 0.f, scc = 0.f;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    Eb += ar[a] * eg[a] + ag[a] * er[a];
+                    sb += ar[a] * ag[a];
+                    Eg += 2.0f * ag[a] * eg[a];
+                    sg += ag[a] * ag[a];
+                }
+                Eb += g3 * sb;
+                Eg += g3 * sg;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+                    const float Ec = ar[a1] * eg[a2] + ag[a2] * er[a1] + ar[a2] * eg[a1] + ag[a1] * er[a2] +
+                                     g2c * (ar[a1] * ag[a2] + ar[a2] * ag[a1]);
+                    const float ac = fabsf(c[a]) + Ec;
+                    Ecc += 2.0f * ac * Ec;
+                    scc += ac * ac;
+                }
+                Ecc += g3 * scc;
+                Eb *= gf;
+                Eg *= gf;
+                Ecc *= gf;
+                const float Et = Eb + B.dt_32 * (1.0f + 2.0f * u) * Eg +
+                                 gf * (3.0f * u * B.dt_32 * (gg + Eg) + 2.0f * u * fabsf(m2));
+                const float Ec3 = Ecc + B.D2_32 * (1.0f + 2.0f * u) * Eg +
+                                  gf * (3.0f * u * B.D2_32 * (gg + Eg) + 2.0f * u * fabsf(m3));
+                const bool rej = (b > Eb) | (m2 > Et) | (m3 > Ec3);
+                if (rej) continue;
+                const bool acc = (b < -Eb) & (m2 < -Et) & (m3 < -Ec3) & (gg > Eg);
+                const float kl = fmaxf(cc - Ecc, 0.0f) / (gg + Eg) * (1.0f - 4.0f * u);
+                const float kh = gg > Eg ? (cc + Ecc) / (gg - Eg) * (1.0f + 4.0f * u) : __builtin_inff();
+                if (kl < lo1) {
+                    lo2 = lo1;
+                    lo1 = kl;
+                    hi1 = kh;
+                    st1 = acc ? 1 : 2;
+                    j1 = j;
+                } else if (kl < lo2) {
+                    lo2 = kl;
+                }
+            }
+            if (st1 == 0) best = -1;
+            else if (st1 == 1 && hi1 < lo2) best = (int32_t)j1;
+            else need = true;
+        }
+    }
+    // undecided particles go to the FP64 recheck
+    push_recheck(p, i, need);
+    if (valid) p.partner[i] = need ? -1 : best;
 }
 
 // FP64 re-search of the particles the screen left undecided.
@@ -1037,6 +1146,7 @@ hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s)
     const uint32_t b = 256;
     if (p.N > 0) k_init_particles<<<blocks_for(p.N, b), b, 0, s>>>(p, d_state);
     k_fill_u32<<<blocks_for(p.C, b) < 4096 ? blocks_for(p.C, b) : 4096, b, 0, s>>>(p.count, p.C, 0u);
+    if (p.N > 0) k_fill_u32<<<4096, b, 0, s>>>(p.sl_cnt, (size_t)p.N, 0u);
     k_init_ctl<<<1, 64, 0, s>>>(p, 0);
     return hipGetLastError();
 }
@@ -1060,13 +1170,18 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     mark(KMC_PHASE_SEARCH);
     const uint32_t gW = blocks_for(p.N, 64);
     if (p.precision == KMC_FP32_SCREEN) {
+        k_vmax_reduce<<<p.nboxes * kVmaxSplit, 256, 0, s>>>(p);
         k_box_bounds<<<blocks_for(p.nboxes, 64), 64, 0, s>>>(p);
-        if (p.N > 0) k_search_wave<PolF32><<<gW, 64, 0, s>>>(p);
-    } else {
-        if (p.N > 0) k_search_wave<PolF64><<<gW, 64, 0, s>>>(p);
+        if (p.N > 0) {
+            k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
+            k_finish32<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
+        }
+    } else if (p.N > 0) {
+        k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
+        k_finish64<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RECHECK);
-    if (p.precision == KMC_FP32_SCREEN && p.N > 0) {
+    if (p.N > 0) {
         k_recheck64<<<512, 256, 0, s>>>(p);
         k_fallback64<<<2048, 256, 0, s>>>(p);
     }

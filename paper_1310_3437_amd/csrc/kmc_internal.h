@@ -15,6 +15,9 @@ constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
 // Partial sums per history row (spreads the per-step count/digest atomics).
 constexpr int kHistLanes = 64;
+// Candidates the search records per particle before the particle falls
+// back to a full search.
+constexpr int kSlots = 8;
 
 // Device copy of one box.  All derived scalars are computed once on the host
 // (L = hi - lo, R2 = R*R) so that every kernel sees the same bits.
@@ -68,8 +71,7 @@ struct Plan {
     unsigned long long* hist_dig;  // [history][kHistLanes]
     double* A;                     // current state, 6*N SoA (previous cell order)
     P64* B;                        // cell-sorted copy of the current state (records)
-    float4* B32a;                  // FP32 screen copy: (x, y, z) - box centre, vx
-    float2* B32b;                  // FP32 screen copy: vy, vz
+    float* vmax_part;              // per scatter block: max |v_k| of its particles this step
     unsigned int* box_vmax;        // per box: max |v_k| this step (FP32 bits)
     BoxStep* box_step;             // per box: screen thresholds this step
     uint32_t* idA;
@@ -77,6 +79,9 @@ struct Plan {
     uint32_t* cell;                // per particle in A order: global cell
     uint32_t* slot;                // per particle in A order: rank inside its cell
     int32_t* partner;              // per sorted particle: sorted index of partner or -1
+    uint32_t* sl_cnt;              // per sorted particle: candidates recorded by the search
+    uint32_t* sl_first;            // per sorted particle: the first of them
+    uint32_t* sl_idx;              // per sorted particle: the next kSlots-1 of them
     uint32_t* boxidx;              // per particle: its box (null when there is one box)
     uint32_t* count;               // per cell: particles (zero between steps)
     uint32_t* start;               // per cell + 1: exclusive prefix of count
@@ -87,6 +92,7 @@ struct Plan {
     uint32_t recheck_cap;
     uint64_t seed;
     int32_t precision, kinematics, block;
+    uint32_t nblk_part;            // scatter blocks (entries of vmax_part)
     float guard;                   // FP32 screen: scale of the rounding-error bounds (>= 1)
 };
 
