@@ -27,12 +27,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s at N=1e8 (FP32-screen vs plain FP64, identical pair lists)"
-# Algorithmic floating-point operations of one pair test (an FMA counts 2):
-# r, g: 6 subtractions; b, g2: 2 x (1 mul + 2 fma) = 10; c = r x g: 3 x
-# (1 mul + 1 fma) = 9; c2: 1 mul + 2 fma = 5; dt*g2, D2*g2: 2.
-FLOP_PER_PAIR_TEST = 32
-PEAK_VALU_TFLOPS = 78.6     # 256 CU x 64 lanes x 2 flop x 2.4 GHz (FP64, or unpacked FP32)
+# Algorithmic floating-point operations of one pair evaluation (an FMA counts
+# 2): r, g: 6 subtractions; b, g2: 2 x (1 mul + 2 fma) = 10; c = r x g:
+# 3 x (1 mul + 1 fma) = 9; c2: 1 mul + 2 fma = 5; dt*g2, D2*g2: 2.  The pair
+# quantities are symmetric, so one evaluation decides both orders of an
+# unordered neighbour pair: the search kernel evaluates pair_tests / 2.
+FLOP_PER_PAIR_EVAL = 32
+PEAK_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, or unpacked FP32)
 PEAK_HBM_GBS = 8000.0
+# Algorithmic HBM bytes per particle-step of the FP64 step (bin 32, scan ~5,
+# sorted copy 116, search 52, resolve/scatter/stream 110).
+STEP_BYTES_PER_PARTICLE = 315
 
 
 def log(*a):
@@ -81,10 +86,12 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests):
     s1 = sim.stats()
     hn, hd = sim.history()
     ms_phase = {k: (s1["ms"][k] - s0["ms"][k]) / steps for k in s1["ms"]}
+    search_kernel_ms = (s1["search_kernel_ms"] - s0["search_kernel_ms"]) / steps
     out = dict(
         value=w.n * steps / el,
         ms_per_step=1e3 * el / steps,
         ms_phase=ms_phase,
+        search_kernel_ms=search_kernel_ms,
         rechecks_per_step=(s1["rechecks"] - s0["rechecks"]) / steps,
         fallbacks=s1["fallbacks"] - s0["fallbacks"],
         history=[(int(a), int(b)) for a, b in zip(hn, hd)],
@@ -93,7 +100,7 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, search {ms_phase['search']:.3f} ms")
+    log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, search kernel {search_kernel_ms:.3f} ms")
     return out
 
 
@@ -124,6 +131,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=1e7)
     ap.add_argument("--paths", default="fp64,fp32")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -157,8 +166,8 @@ def main():
         identical = results["fp64"]["history"] == results["fp32"]["history"]
     head = results.get("fp32") or results["fp64"]
     head_name = "fp32_screen" if "fp32" in results else "fp64"
-    search_ms = head["ms_phase"]["search"] + head["ms_phase"]["recheck"]
-    flops = FLOP_PER_PAIR_TEST * head["pair_tests"]
+    search_ms = head["search_kernel_ms"]
+    flops = FLOP_PER_PAIR_EVAL * head["pair_tests"] / 2
     achieved = flops / (search_ms * 1e-3) / 1e12
     traffic = traffic_for(head_name, None)
     line = {
@@ -182,16 +191,24 @@ def main():
             "path": head_name,
         },
         "roofline": {
-            "kernel": "partner search" + (" (FP32 screen + FP64 recheck)" if head_name == "fp32_screen" else " (FP64)"),
+            "kernel": "k_search_half<" + ("PolF32> (FP32 screen)" if head_name == "fp32_screen" else "PolF64> (FP64)"),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU_TFLOPS,
             "traffic": traffic,
-            "flop_per_pair_test": FLOP_PER_PAIR_TEST,
-            "pair_tests_per_launch": head["pair_tests"],
+            "flop_per_pair_eval": FLOP_PER_PAIR_EVAL,
+            "pair_evals_per_launch": head["pair_tests"] // 2,
             "avg_launch_ms": search_ms,
+        },
+        "roofline_step": {
+            "bound": "hbm",
+            "achieved": STEP_BYTES_PER_PARTICLE * n / (head["ms_per_step"] * 1e-3) / 1e9,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": STEP_BYTES_PER_PARTICLE * n / (head["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
         },
         "pair_tests_per_s": head["pair_tests"] * head["value"] / n,
         "identical_pair_lists": identical,
@@ -199,6 +216,14 @@ def main():
     }
     if "fp64" in results and "fp32" in results:
         line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if args.copy_calibration:
+        src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 1 << 31
+        del src, dst
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
     print(json.dumps(line), flush=True)

@@ -117,10 +117,11 @@ enum {
     KMC_PHASE_BIN = 0,      /* cell index + per-cell count                          */
     KMC_PHASE_SCAN = 1,     /* exclusive prefix sum of the counts                   */
     KMC_PHASE_SCATTER = 2,  /* cell-sorted copy of the state                        */
-    KMC_PHASE_SEARCH = 3,   /* DCA partner search (FP64, or the FP32 screen)        */
-    KMC_PHASE_RECHECK = 4,  /* FP64 re-search of the screen's undecided particles   */
-    KMC_PHASE_RESOLVE = 5,  /* mutual check, scatter, free stream, boundaries       */
-    KMC_PHASE_COUNT = 6
+    KMC_PHASE_SEARCH = 3,   /* DCA pair search kernel (FP64, or the FP32 screen)    */
+    KMC_PHASE_FINISH = 4,   /* closest partner from the recorded candidates         */
+    KMC_PHASE_RECHECK = 5,  /* full FP64 re-search of undecided particles           */
+    KMC_PHASE_RESOLVE = 6,  /* mutual check, scatter, free stream, boundaries       */
+    KMC_PHASE_COUNT = 7
 };
 
 typedef struct kmc_stats {
@@ -131,6 +132,10 @@ typedef struct kmc_stats {
     uint64_t fallbacks;        /* steps whose recheck list overflowed                   */
     double ms[8];              /* accumulated milliseconds per phase (profile mode)      */
     uint64_t timed_steps;      /* steps that contributed to ms                          */
+    double search_kernel_ms;   /* accumulated milliseconds of the search kernel alone   */
+    uint64_t candidates;       /* pairs the search recorded per particle, summed over
+                                  particles and steps (FP64: acceptable pairs; FP32
+                                  screen: pairs it could not reject)                    */
 } kmc_stats;
 
 typedef struct kmc_ctx kmc_ctx;

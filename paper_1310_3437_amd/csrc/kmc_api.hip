@@ -28,6 +28,7 @@ struct kmc_ctx {
     std::vector<hipEvent_t> ev_free;
     std::vector<std::vector<hipEvent_t>> ev_pending;
     double ms[8] = {0};
+    double search_kernel_ms = 0;
     uint64_t timed_steps = 0;
 };
 
@@ -127,7 +128,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     const uint32_t nblk_part = (uint32_t)((N + blk - 1) / blk);
     p.vmax_part = (float*)take(sizeof(float) * (nblk_part ? nblk_part : 1));
     p.box_vmax = (unsigned int*)take(sizeof(unsigned int) * nboxes);
-    p.box_step = (BoxStep*)take(sizeof(BoxStep) * nboxes);
+    p.box_sb = (ScreenBounds*)take(sizeof(ScreenBounds) * nboxes);
     p.idA = (uint32_t*)take(4 * N);
     p.idB = (uint32_t*)take(4 * N);
     p.cell = (uint32_t*)take(4 * N);
@@ -141,12 +142,15 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.start = (uint32_t*)take(4 * (C + 1));
     p.partial = (uint32_t*)take(4 * (size_t)(nblk ? nblk : 1));
     p.recheck = (uint32_t*)take(4 * (size_t)(cap ? cap : 1));
+    p.ovf = (uint2*)take(sizeof(uint2) * 2 * (N ? N : 1));
+    p.cand_acc = (unsigned long long*)take(sizeof(unsigned long long) * kHistLanes);
     p.N = (uint32_t)N;
     p.C = (uint32_t)C;
     p.nboxes = nboxes;
     p.H = H;
     p.nblk_scan = nblk;
     p.recheck_cap = cap;
+    p.ovf_cap = (uint32_t)(N ? 2 * N : 1);
     p.seed = cfg.seed;
     p.precision = cfg.precision;
     p.kinematics = cfg.kinematics;
@@ -202,6 +206,9 @@ void fold_events(kmc_ctx* c)
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, set[k], set[k + 1]) == hipSuccess) c->ms[k] += ms;
         }
+        float ks = 0.f;
+        if (hipEventElapsedTime(&ks, set[KMC_PHASE_COUNT + 1], set[KMC_PHASE_FINISH]) == hipSuccess)
+            c->search_kernel_ms += ks;
         c->timed_steps += 1;
         for (auto e : set) c->ev_free.push_back(e);
     }
@@ -303,7 +310,7 @@ int kmc_step(kmc_ctx* c, uint32_t nsteps, void* stream)
         if (graph) {
             e = hipGraphLaunch(c->exec, s);
         } else if (c->cfg.profile) {
-            std::vector<hipEvent_t> set(KMC_PHASE_COUNT + 1);
+            std::vector<hipEvent_t> set(KMC_PHASE_COUNT + 2);
             for (auto& ev : set) {
                 if (!c->ev_free.empty()) { ev = c->ev_free.back(); c->ev_free.pop_back(); }
                 else if (hipEventCreate(&ev) != hipSuccess) return KMC_EDEVICE;
@@ -390,7 +397,17 @@ int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
     out->cells_total = c->plan.C;
     out->rechecks = ctl.rechecks_total;
     out->fallbacks = ctl.fallbacks_total;
+    {
+        unsigned long long acc[kHistLanes];
+        if (hipMemcpyAsync(acc, c->plan.cand_acc, sizeof(acc), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return KMC_EDEVICE;
+        uint64_t tot = 0;
+        for (int l = 0; l < kHistLanes; ++l) tot += acc[l];
+        out->candidates = tot;
+    }
     for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
+    out->search_kernel_ms = c->search_kernel_ms;
     out->timed_steps = c->timed_steps;
     return KMC_OK;
 }

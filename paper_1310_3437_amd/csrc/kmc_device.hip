@@ -210,6 +210,7 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
     for (uint32_t k = t; k < (uint32_t)kHistLanes; k += blockDim.x) {
         p.hist_np[k] = 0;
         p.hist_dig[k] = 0;
+        p.cand_acc[k] = 0;
     }
 }
 
@@ -331,6 +332,7 @@ __global__ __launch_bounds__(1024) void k_scan_partials(Plan p)
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
         p.ctl->work_next = 0;
+        p.ctl->ovf_count = 0;
     }
     for (uint32_t b = threadIdx.x; b < p.nboxes; b += blockDim.x) p.box_vmax[b] = 0u;
 }
@@ -427,56 +429,6 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
     if (threadIdx.x == 0 && red[0] > 0.f) atomicMax(&p.box_vmax[b], __float_as_uint(red[0]));
 }
 
-// Loose screen thresholds of every box for this step (FP64 arithmetic,
-// rounded up).  They bound, over every neighbour pair of the box, the
-// difference between the FP32 screen's b, -b - dt g2, c2 - D2 g2 and the
-// FP64 definition's, from worst-case magnitudes |r_k| <= 2 h_k and
-// |v_k| <= V (standard forward error analysis of sums and products,
-// Higham 2002, ch. 3), times the guard factor.
-__global__ void k_box_bounds(Plan p)
-{
-    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= p.nboxes) return;
-    const BoxDev& B = p.boxes[b];
-    const float vm = __uint_as_float(p.box_vmax[b]);
-    const double u = 0x1.0p-24, u64 = 0x1.0p-53;
-    const double g3 = 3.0 * u / (1.0 - 3.0 * u) + 3.0 * u64 / (1.0 - 3.0 * u64);
-    const double g2 = 2.0 * u / (1.0 - 2.0 * u) + 2.0 * u64 / (1.0 - 2.0 * u64);
-    const double V = (double)vm * (1.0 + 3.0 * u);
-    const double eg = 4.0001 * u * V;
-    const double G = 2.0 * V;
-    double R[3], er[3];
-    for (int k = 0; k < 3; ++k) { R[k] = B.rmax[k]; er[k] = (double)B.er[k]; }
-    double Eb = 0, Eg2 = 0, Ec2 = 0, sb = 0, sg = 0, sc = 0;
-    for (int k = 0; k < 3; ++k) {
-        Eb += R[k] * eg + G * er[k] + er[k] * eg;
-        sb += (R[k] + er[k]) * (G + eg);
-        Eg2 += 2.0 * G * eg + eg * eg;
-        sg += (G + eg) * (G + eg);
-    }
-    Eb += g3 * sb;
-    Eg2 += g3 * sg;
-    for (int k = 0; k < 3; ++k) {
-        const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
-        const double C = R[k1] * G + R[k2] * G;
-        const double Ec = (R[k1] * eg + G * er[k1] + er[k1] * eg) + (R[k2] * eg + G * er[k2] + er[k2] * eg) +
-                          g2 * ((R[k1] + er[k1]) * (G + eg) + (R[k2] + er[k2]) * (G + eg));
-        Ec2 += 2.0 * C * Ec + Ec * Ec;
-        sc += (C + Ec) * (C + Ec);
-    }
-    Ec2 += g3 * sc;
-    const double G2max = 3.0 * (G + eg) * (G + eg);
-    const double Et = Eb + B.dt * (1.0 + u) * Eg2 + 3.0 * u * B.dt * G2max;
-    const double Ecc = Ec2 + B.D2 * (1.0 + u) * Eg2 + 3.0 * u * B.D2 * G2max;
-    const double f = (double)p.guard * (1.0 + 1e-5);
-    BoxStep st;
-    st.Tb = (float)(f * Eb);
-    st.Tt = (float)(f * Et);
-    st.Tc = (float)(f * Ecc);
-    st.vmax = (float)V;
-    p.box_step[b] = st;
-}
-
 // --------------------------------------------------------------------------
 // a4: DCA partner search.
 //
@@ -548,6 +500,11 @@ __device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64&
     }
 }
 
+// Flag on a recorded candidate index: the FP32 screen proved the pair
+// acceptable in FP64 (particle indices stay below 2^31).
+constexpr uint32_t kSureBit = 0x80000000u;
+constexpr uint32_t kIdxMask = 0x7FFFFFFFu;
+
 // Slot k of particle i's candidate list (slot 0 lives in a dense array: most
 // particles have at most one candidate).
 __device__ __forceinline__ uint32_t* slot_ptr(const Plan& p, uint32_t i, uint32_t k)
@@ -555,18 +512,22 @@ __device__ __forceinline__ uint32_t* slot_ptr(const Plan& p, uint32_t i, uint32_
     return k == 0 ? p.sl_first + i : p.sl_idx + (size_t)i * (kSlots - 1) + (k - 1);
 }
 
-// Record the unordered pair {i, j} in the candidate lists of both.
-__device__ __forceinline__ void record_pair(const Plan& p, uint32_t i, uint32_t j)
+// Record the unordered pair {i, j} in the candidate lists of both; jf is j
+// with the screen's flag bit, which both entries carry.
+__device__ __forceinline__ void record_pair(const Plan& p, uint32_t i, uint32_t jf)
 {
+    const uint32_t j = jf & kIdxMask, flag = jf & kSureBit;
     uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
-    if (k < (uint32_t)kSlots) *slot_ptr(p, i, k) = j;
+    if (k < (uint32_t)kSlots) *slot_ptr(p, i, k) = jf;
     k = atomicAdd(&p.sl_cnt[j], 1u);
-    if (k < (uint32_t)kSlots) *slot_ptr(p, j, k) = i;
+    if (k < (uint32_t)kSlots) *slot_ptr(p, j, k) = i | flag;
 }
 
 // Pairs a lane found, kept in registers until the end of the wave's search
 // (a global atomic inside the search loop would stall the whole wave); a
-// lane that finds more records the excess at once.
+// lane that finds more appends the excess to the step's overflow pair list
+// (one counter, distributed by k_distribute_overflow), or raises the
+// overflow flag when that list is full (whole-step FP64 fallback).
 constexpr int kReg = 4;
 
 struct Found {
@@ -579,7 +540,9 @@ struct Found {
             for (int k = 0; k < kReg; ++k) j[k] = (n == k) ? jj : j[k];
             ++n;
         } else {
-            record_pair(p, i, jj);
+            const uint32_t idx = atomicAdd(&p.ctl->ovf_count, 1u);
+            if (idx < p.ovf_cap) p.ovf[idx] = make_uint2(i, jj);
+            else atomicOr(&p.ctl->overflow, 1u);
         }
     }
     // append the kept pairs to both candidate lists
@@ -591,11 +554,16 @@ struct Found {
         for (int k = 0; k < kReg; ++k) {
             if (k < n) {
                 if (base + k < (uint32_t)kSlots) *slot_ptr(p, i, base + k) = j[k];
-                const uint32_t q = atomicAdd(&p.sl_cnt[j[k]], 1u);
-                if (q < (uint32_t)kSlots) *slot_ptr(p, j[k], q) = i;
+                const uint32_t jj = j[k] & kIdxMask;
+                const uint32_t q = atomicAdd(&p.sl_cnt[jj], 1u);
+                if (q < (uint32_t)kSlots) *slot_ptr(p, jj, q) = i | (j[k] & kSureBit);
             }
         }
     }
+};
+
+// Per-group context of the search (the FP64 search needs none).
+struct NoGroup {
 };
 
 struct PolF64 {
@@ -606,16 +574,21 @@ struct PolF64 {
     struct Own {
         P64 me;
     };
+    using Group = NoGroup;
+    __device__ static void begin_group(const Plan&, const BoxDev&, Own&, Group&, int, int, int, int, int) {}
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         o.me = p.B[i];
         x = o.me.x; y = o.me.y; z = o.me.z;
     }
-    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev&) { l.rec[t] = p.B[j]; }
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev&, const Group&,
+                                 int, int, int)
+    {
+        l.rec[t] = p.B[j];
+    }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
-                                const Own& o, const BoxDev& B, const BoxStep& /*st*/, int wx, int wy, int wz,
-                                Found& f)
+                                const Own& o, const BoxDev& B, const Group&, int wx, int wy, int wz, Found& f)
     {
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         const double D2 = B.D2, dt = B.dt;
@@ -629,60 +602,167 @@ struct PolF64 {
     }
 };
 
-// FP32 screen: a candidate is dropped only when the FP64 definition is
-// certain to reject it (thresholds from the per-box bounds of this step).
+// FP32 screen.  Positions are rounded to FP32 relative to the centre X0 of
+// the group's neighbourhood (periodic images added in FP64 first), so their
+// rounding error is u times the neighbourhood size, not the box size.  The
+// screen tests the Lagrange form d_min^2 g2 = |r|^2 g2 - b^2 (cheaper than the
+// cross product) and drops a pair only when the FP64 definition is certain to
+// reject it; every pair it keeps is decided exactly in FP64 afterwards.
+struct ScreenGroup {
+    double X0[3];
+    ScreenBounds t;
+};
+
+// Bounds on |screen value - FP64 definition value| for every neighbour pair
+// of any search group of the box (forward error analysis, Higham 2002,
+// ch. 3).  Inputs: |r_k| <= R_k = 2 h_k; FP32 position errors
+// e_r,k = u (2 P_k + 2 R_k) with positions relative to the group centre X0
+// (a group spans at most 64 cells along x, so |x - X0| <= P_x = 33 h_x,
+// P_y = 1.5 h_y, P_z = 1.5 h_z) plus the FP64 definition's own input
+// rounding; velocity-difference error e_g = 4 u V.
+// With q = sqrt(g2_hat) (kappa q bounds every |g_hat_k|):
+//   |db|   <= b0 + b1 q
+//   |dg2|  <= g0 + g1 q + g2c q^2
+//   |dm2|  <= P0 + P1 q + P2 q^2          (m2 = -b - dt g2)
+//   |dm3|  <= A0 + A1 q + A2 q^2          (m3 = (|r|^2 - D2) g2 - b^2, Lagrange form
+//                                          of the definition's c2 - D2 g2)
+// and q <= (q^2 / G0 + G0) / 2 for any G0 > 0 makes each bound affine in
+// g2_hat.  gamma terms cover the rounding of every sum and product in both
+// precisions; the guard factor scales the result.
+__device__ __forceinline__ void screen_thresholds(const BoxDev& B, const double P[3], double V, float guard,
+                                                  ScreenBounds& g)
+{
+    const double u = 0x1.0p-24, u64 = 0x1.0p-53;
+    const double g3 = 3.0 * u / (1.0 - 3.0 * u) + 3.0 * u64 / (1.0 - 3.0 * u64);
+    const double kap = 1.0 + g3;
+    const double eg = 4.0001 * u * V + 4.0 * u64 * V;
+    double SE = 0, SRE = 0, RR = 0, Err = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double R = B.rmax[k];
+        const double er = u * (2.0 * P[k] + 2.0 * R) * (1.0 + 1e-5) + 2.0 * u64 * (R + 2.0 * B.L[k]);
+        SE += er;
+        SRE += R + er;
+        RR += (R + er) * (R + er);
+        Err += 2.0 * R * er + er * er;
+    }
+    Err += g3 * RR;
+    const double Rn = sqrt(RR) * (1.0 + 1e-12);
+    const double s3 = 1.7320508075688774;     // >= sqrt(3)
+    const double D2 = B.D2, dt = B.dt;
+    const double b0 = eg * (SRE + SE), b1 = kap * (SE + g3 * SRE);
+    const double g0 = 3.0 * eg * eg, g1 = 2.0 * s3 * kap * eg, g2c = g3 * kap * kap;
+    const double Et = Err + u * D2 + u * (RR + D2);
+    const double Tm = RR + D2 + Et;
+    const double A2 = 2.0 * Rn * kap * b1 + b1 * b1 + u * RR * kap * kap * (1.0 + g3) * (1.0 + g3) + Tm * g2c +
+                      Et * (1.0 + g2c) + 128.0 * u64 * (RR + D2) * kap * kap;
+    const double A1 = 2.0 * Rn * (kap * b0 + s3 * eg * b1) + 2.0 * b0 * b1 + Tm * g1 + Et * g1;
+    const double A0 = 2.0 * Rn * s3 * eg * b0 + b0 * b0 + Tm * g0 + Et * g0 + 384.0 * u64 * (RR + D2) * eg * eg;
+    const double dtf = dt * (1.0 + 2.0 * u64);
+    const double P0 = b0 + dtf * g0, P1 = b1 + dtf * g1, P2 = dtf * g2c + (u + u64) * dt;
+    const double G0 = V > 0.0 ? 0.25 * V : 1.0;
+    const double f = (double)guard * (1.0 + 1e-5) * (1.0 + 1e-6);
+    g.tb0 = (float)(f * (b0 + 0.5 * b1 * G0));
+    g.tb1 = (float)(f * (0.5 * b1 / G0));
+    g.tt0 = (float)(f * (P0 + 0.5 * P1 * G0));
+    g.tt1 = (float)(f * (P2 + 0.5 * P1 / G0));
+    g.tc0 = (float)(f * (A0 + 0.5 * A1 * G0));
+    g.tc1 = (float)(f * (A2 + 0.5 * A1 / G0));
+    g.tg0 = (float)(f * (g0 + 0.5 * g1 * G0));
+    g.tg1 = (float)(f * (g2c + 0.5 * g1 / G0));
+}
+
+__global__ void k_screen_bounds(Plan p)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= p.nboxes) return;
+    const BoxDev& B = p.boxes[b];
+    double P[3];
+    const double cells[3] = {66.0, 3.0, 3.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double h = B.L[k] / (double)B.nc[k];
+        P[k] = 0.5 * cells[k] * h * (1.0 + 1e-9) + 1e-12 * (fabs(B.lo[k]) + fabs(B.hi[k]) + 2.0 * B.L[k]);
+    }
+    const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * 0x1.0p-24);
+    screen_thresholds(B, P, V, p.guard, p.box_sb[b]);
+}
+
+
+struct alignas(16) Rec32 {
+    float4 a;   // x, y, z relative to the group centre; vx
+    float2 b;   // vy, vz
+    float2 pad;
+};
+
 struct PolF32 {
-    static constexpr int W = 192;         // staged records per chunk (4.5 KiB)
+    static constexpr int W = 160;         // staged records per chunk (5 KiB)
     struct Lds {
-        float4 a[W];
-        float2 b[W];
+        Rec32 r[W];
     };
     struct Own {
         float x, y, z, vx, vy, vz;
+        double X, Y, Z;
     };
+    using Group = ScreenGroup;
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         const P64 m = p.B[i];
-        const BoxDev& B = box_of(p, i);
-        o.x = (float)(m.x - (double)B.ctr32[0]);
-        o.y = (float)(m.y - (double)B.ctr32[1]);
-        o.z = (float)(m.z - (double)B.ctr32[2]);
+        o.X = m.x; o.Y = m.y; o.Z = m.z;
         o.vx = (float)m.vx; o.vy = (float)m.vy; o.vz = (float)m.vz;
         x = m.x; y = m.y; z = m.z;
     }
-    // FP32 screen copy of a record: position relative to the box centre and
-    // velocity, each rounded once to FP32 (the candidates staged belong to the
-    // box of the staging group)
-    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev& B)
+    // Centre and thresholds of the group whose cells are x in [cxf, cxl] of
+    // row (gcy, gcz); its neighbourhood spans cells cxf-1..cxl+1, gcy-1..gcy+1,
+    // gcz-1..gcz+1 (images included).
+    __device__ static void begin_group(const Plan& p, const BoxDev& B, Own& o, Group& g, int cxf, int cxl,
+                                       int gcy, int gcz, int gb)
+    {
+        const int clo[3] = {cxf - 1, gcy - 1, gcz - 1}, chi[3] = {cxl + 1, gcy + 1, gcz + 1};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double h = B.L[k] / (double)B.nc[k];
+            g.X0[k] = B.lo[k] + 0.5 * (double)(clo[k] + chi[k] + 1) * h;
+        }
+        g.t = p.box_sb[gb];
+        o.x = (float)(o.X - g.X0[0]);
+        o.y = (float)(o.Y - g.X0[1]);
+        o.z = (float)(o.Z - g.X0[2]);
+    }
+    // FP32 copy of a candidate: image-shifted position relative to X0 and
+    // velocity, each rounded once
+    __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev& B, const Group& g,
+                                 int wx, int wy, int wz)
     {
         const P64 q = p.B[j];
-        l.a[t] = make_float4((float)(q.x - (double)B.ctr32[0]), (float)(q.y - (double)B.ctr32[1]),
-                             (float)(q.z - (double)B.ctr32[2]), (float)q.vx);
-        l.b[t] = make_float2((float)q.vy, (float)q.vz);
+        const double sx = wx ? (double)wx * B.L[0] : 0.0, sy = wy ? (double)wy * B.L[1] : 0.0,
+                     sz = wz ? (double)wz * B.L[2] : 0.0;
+        l.r[t].a = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
+                               (float)((q.z + sz) - g.X0[2]), (float)q.vx);
+        l.r[t].b = make_float2((float)q.vy, (float)q.vz);
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
-                                const Own& o, const BoxDev& B, const BoxStep& st, int wx, int wy, int wz,
-                                Found& f)
+                                const Own& o, const BoxDev& B, const Group& g, int, int, int, Found& f)
     {
-        const float sx = (float)wx * B.L32[0], sy = (float)wy * B.L32[1], sz = (float)wz * B.L32[2];
         const float D2 = B.D2_32, dt = B.dt_32;
-        const float Tb = st.Tb, Tt = st.Tt, Tc = st.Tc;
+        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, tt1 = g.t.tt1, tc0 = g.t.tc0, tc1 = g.t.tc1;
         for (uint32_t j = j0; j < j1; ++j) {
-            const float4 qa = l.a[j - c0];
-            const float2 qb = l.b[j - c0];
-            float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
-            if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const float4 qa = l.r[j - c0].a;
+            const float2 qb = l.r[j - c0].b;
+            const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-            const float cx = fmaf(ry, gz, -(rz * gy));
-            const float cy = fmaf(rz, gx, -(rx * gz));
-            const float cz = fmaf(rx, gy, -(ry * gx));
-            const float c2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+            const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
             const float m2 = fmaf(-dt, g2, -b);
-            const float m3 = fmaf(-D2, g2, c2);
-            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) f.add(p, i, j);
+            const float m3 = fmaf(rr - D2, g2, -(b * b));
+            const float Tb = fmaf(tb1, g2, tb0), Tt = fmaf(tt1, g2, tt0), Tc = fmaf(tc1, g2, tc0);
+            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) {
+                // certainly acceptable in FP64: recorded with the flag bit
+                const bool sure = (b < -Tb) & (m2 < -Tt) & (m3 < -Tc) & (g2 > fmaf(g.t.tg1, g2, g.t.tg0));
+                f.add(p, i, j | (sure ? kSureBit : 0u));
+            }
         }
     }
 };
@@ -726,10 +806,11 @@ void k_search_half(Plan p)
         const int last = 63 - __clzll((long long)grp);
         const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
         const BoxDev& B = p.boxes[gb];
-        const BoxStep st = p.box_step[gb];
         const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
         const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
+        typename Pol::Group gctx;
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb);
         // Cells [ca, cb] of a row seen with image shift (wx, wy, wz); each lane
         // tests the sub-range [ls, le) of it (empty when ls >= le).
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
@@ -737,11 +818,11 @@ void k_search_half(Plan p)
             const bool sh = (wx | wy | wz) != 0;
             for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
                 const uint32_t n = min((uint32_t)Pol::W, ge - c0);
-                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t, B);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz);
                 __syncthreads();
                 const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
-                if (sh) Pol::template scan<true>(p, lds, c0, j0, j1, i, own, B, st, wx, wy, wz, found);
-                else Pol::template scan<false>(p, lds, c0, j0, j1, i, own, B, st, wx, wy, wz, found);
+                if (sh) Pol::template scan<true>(p, lds, c0, j0, j1, i, own, B, gctx, wx, wy, wz, found);
+                else Pol::template scan<false>(p, lds, c0, j0, j1, i, own, B, gctx, wx, wy, wz, found);
                 __syncthreads();
             }
         };
@@ -785,6 +866,17 @@ void k_search_half(Plan p)
     if (valid) found.flush(p, i);
 }
 
+// Pairs beyond a search lane's register slots, into both candidate lists.
+__global__ void k_distribute_overflow(Plan p)
+{
+    const uint32_t cnt = p.ctl->ovf_count;
+    const uint32_t n = cnt < p.ovf_cap ? cnt : p.ovf_cap;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const uint2 e = p.ovf[k];
+        record_pair(p, e.x, e.y);
+    }
+}
+
 // Wave-aggregated append of this lane's particle to the FP64 recheck list
 // (all lanes of the wave must call it).
 __device__ __forceinline__ void push_recheck(const Plan& p, uint32_t i, bool need)
@@ -803,28 +895,36 @@ __device__ __forceinline__ void push_recheck(const Plan& p, uint32_t i, bool nee
     }
 }
 
-// Partner of every particle from its recorded candidates (FP64: all of
-// them are acceptable; the (key, id) minimum is taken with exact keys).
-__global__ __launch_bounds__(256) void k_finish64(Plan p)
+// Partner of every particle from its recorded candidates: the exact FP64
+// (key, id) minimum over those the definition accepts.  The FP64 search
+// records only acceptable pairs (CHECK = false: a single candidate is the
+// partner); the FP32 screen records every pair it could not reject
+// (CHECK = true: each is tested exactly).  A particle with more candidates
+// than slots is searched again in full.
+template <bool CHECK>
+__global__ __launch_bounds__(256) void k_finish(Plan p)
 {
+    __shared__ uint64_t red[32];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < p.N;
     const uint32_t cnt = valid ? p.sl_cnt[i] : 0u;
     int32_t best = -1;
     if (cnt != 0) p.sl_cnt[i] = 0u;
-    if (cnt == 1) {
-        best = (int32_t)p.sl_first[i];
-    } else if (cnt > 1 && cnt <= (uint32_t)kSlots) {
+    const uint32_t first = cnt == 1 ? p.sl_first[i] : 0u;
+    if (cnt == 1 && (!CHECK || (first & kSureBit))) {
+        best = (int32_t)(first & kIdxMask);
+    } else if (cnt >= 1 && cnt <= (uint32_t)kSlots) {
         const BoxDev& B = box_of(p, i);
         const P64 me = p.B[i];
         double best_key = __builtin_inf();
         uint32_t best_id = 0xFFFFFFFFu;
         for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t j = *slot_ptr(p, i, k);
+            const uint32_t j = *slot_ptr(p, i, k) & kIdxMask;
             const P64 q = p.B[j];
             double r[3];
             rel64(B, me, q, r);
             const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            if (CHECK && !accept(pq, B.D2, B.dt)) continue;
             const double key = pq.c2 / pq.g2;
             const uint32_t idj = p.idB[j];
             if (key < best_key || (key == best_key && idj < best_id)) {
@@ -834,124 +934,11 @@ __global__ __launch_bounds__(256) void k_finish64(Plan p)
             }
         }
     }
-    // more candidates than slots: the particle is searched again in full
-    const bool need = cnt > (uint32_t)kSlots;
-    push_recheck(p, i, need);
+    push_recheck(p, i, cnt > (uint32_t)kSlots);
     if (valid) p.partner[i] = best;
-}
-
-// FP32 screen finish: every recorded candidate is classified with per-pair
-// rounding-error bounds (Higham 2002, ch. 3) into certainly rejected,
-// certainly accepted or undecided by the FP64 definition, with an interval
-// that certainly contains its FP64 key.  The partner is certain when the
-// candidate with the lowest key bound is certainly accepted and its upper
-// bound lies below every other candidate's lower bound; otherwise the
-// particle is appended to the FP64 recheck list.
-__global__ __launch_bounds__(256) void k_finish32(Plan p)
-{
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < p.N;
-    bool need = false;
-    int32_t best = -1;
-    if (valid) {
-        const uint32_t cnt = p.sl_cnt[i];
-        if (cnt != 0) p.sl_cnt[i] = 0u;
-        if (cnt > (uint32_t)kSlots) {
-            need = true;
-        } else if (cnt > 0) {
-            const BoxDev& B = box_of(p, i);
-            const float u = 0x1.0p-24f;
-            const float g3 = 3.0f * u * 1.001f + 4e-16f;
-            const float g2c = 2.0f * u * 1.001f + 3e-16f;
-            const float gf = p.guard * 1.001f;
-            float lo1 = __builtin_inff(), hi1 = __builtin_inff(), lo2 = __builtin_inff();
-            int st1 = 0;                       // 0 none, 1 accepted, 2 undecided
-            uint32_t j1 = 0;
-            const P64 mi = p.B[i];
-            const double xi[3] = {mi.x, mi.y, mi.z};
-            const float pi[3] = {(float)(mi.x - (double)B.ctr32[0]), (float)(mi.y - (double)B.ctr32[1]),
-                                 (float)(mi.z - (double)B.ctr32[2])};
-            const float vi[3] = {(float)mi.vx, (float)mi.vy, (float)mi.vz};
-            for (uint32_t k = 0; k < cnt; ++k) {
-                const uint32_t j = *slot_ptr(p, i, k);
-                const P64 qj = p.B[j];
-                const double xj[3] = {qj.x, qj.y, qj.z};
-                const float pj[3] = {(float)(qj.x - (double)B.ctr32[0]), (float)(qj.y - (double)B.ctr32[1]),
-                                     (float)(qj.z - (double)B.ctr32[2])};
-                const float vj[3] = {(float)qj.vx, (float)qj.vy, (float)qj.vz};
-                float r[3], g[3], ar[3], ag[3], eg[3], er[3];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int ci = cell1(xi[a], B.lo[a], B.inv_h[a], B.nc[a]);
-                    const int cj = cell1(xj[a], B.lo[a], B.inv_h[a], B.nc[a]);
-                    const int w = wrap_of(ci, cj, B.nc[a], B.periodic[a]);
-                    r[a] = pj[a] - pi[a];
-                    if (w != 0) r[a] = r[a] + (float)w * B.L32[a];
-                    g[a] = vj[a] - vi[a];
-                    er[a] = B.er[a];
-                    eg[a] = u * 1.0001f * (fabsf(vi[a]) + fabsf(vj[a]) + fabsf(g[a]));
-                    ar[a] = fabsf(r[a]) + er[a];
-                    ag[a] = fabsf(g[a]) + eg[a];
-                }
-                const float b = fmaf(r[2], g[2], fmaf(r[1], g[1], r[0] * g[0]));
-                const float gg = fmaf(g[2], g[2], fmaf(g[1], g[1], g[0] * g[0]));
-                float c[3];
-                c[0] = fmaf(r[1], g[2], -(r[2] * g[1]));
-                c[1] = fmaf(r[2], g[0], -(r[0] * g[2]));
-                c[2] = fmaf(r[0], g[1], -(r[1] * g[0]));
-                const float cc = fmaf(c[2], c[2], fmaf(c[1], c[1], c[0] * c[0]));
-                const float m2 = fmaf(-B.dt_32, gg, -b);
-                const float m3 = fmaf(-B.D2_32, gg, cc);
-                float Eb = 0.f, Eg = 0.f, sb = 0.f, sg = 0.f, Ecc = 0.f, scc = 0.f;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    Eb += ar[a] * eg[a] + ag[a] * er[a];
-                    sb += ar[a] * ag[a];
-                    Eg += 2.0f * ag[a] * eg[a];
-                    sg += ag[a] * ag[a];
-                }
-                Eb += g3 * sb;
-                Eg += g3 * sg;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
-                    const float Ec = ar[a1] * eg[a2] + ag[a2] * er[a1] + ar[a2] * eg[a1] + ag[a1] * er[a2] +
-                                     g2c * (ar[a1] * ag[a2] + ar[a2] * ag[a1]);
-                    const float ac = fabsf(c[a]) + Ec;
-                    Ecc += 2.0f * ac * Ec;
-                    scc += ac * ac;
-                }
-                Ecc += g3 * scc;
-                Eb *= gf;
-                Eg *= gf;
-                Ecc *= gf;
-                const float Et = Eb + B.dt_32 * (1.0f + 2.0f * u) * Eg +
-                                 gf * (3.0f * u * B.dt_32 * (gg + Eg) + 2.0f * u * fabsf(m2));
-                const float Ec3 = Ecc + B.D2_32 * (1.0f + 2.0f * u) * Eg +
-                                  gf * (3.0f * u * B.D2_32 * (gg + Eg) + 2.0f * u * fabsf(m3));
-                const bool rej = (b > Eb) | (m2 > Et) | (m3 > Ec3);
-                if (rej) continue;
-                const bool acc = (b < -Eb) & (m2 < -Et) & (m3 < -Ec3) & (gg > Eg);
-                const float kl = fmaxf(cc - Ecc, 0.0f) / (gg + Eg) * (1.0f - 4.0f * u);
-                const float kh = gg > Eg ? (cc + Ecc) / (gg - Eg) * (1.0f + 4.0f * u) : __builtin_inff();
-                if (kl < lo1) {
-                    lo2 = lo1;
-                    lo1 = kl;
-                    hi1 = kh;
-                    st1 = acc ? 1 : 2;
-                    j1 = j;
-                } else if (kl < lo2) {
-                    lo2 = kl;
-                }
-            }
-            if (st1 == 0) best = -1;
-            else if (st1 == 1 && hi1 < lo2) best = (int32_t)j1;
-            else need = true;
-        }
-    }
-    // undecided particles go to the FP64 recheck
-    push_recheck(p, i, need);
-    if (valid) p.partner[i] = need ? -1 : best;
+    uint64_t c64 = cnt, z = 0;
+    block_sum2(c64, z, red);
+    if (threadIdx.x == 0 && c64) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c64);
 }
 
 // FP64 re-search of the particles the screen left undecided.
@@ -1171,14 +1158,18 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     const uint32_t gW = blocks_for(p.N, 64);
     if (p.precision == KMC_FP32_SCREEN) {
         k_vmax_reduce<<<p.nboxes * kVmaxSplit, 256, 0, s>>>(p);
-        k_box_bounds<<<blocks_for(p.nboxes, 64), 64, 0, s>>>(p);
-        if (p.N > 0) {
-            k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
-            k_finish32<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
-        }
-    } else if (p.N > 0) {
-        k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
-        k_finish64<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
+        k_screen_bounds<<<blocks_for(p.nboxes, 64), 64, 0, s>>>(p);
+    }
+    if (ev) (void)hipEventRecord(ev[KMC_PHASE_COUNT + 1], s);   // search kernel alone
+    if (p.N > 0) {
+        if (p.precision == KMC_FP32_SCREEN) k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
+        else k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
+    }
+    mark(KMC_PHASE_FINISH);
+    if (p.N > 0) k_distribute_overflow<<<256, 256, 0, s>>>(p);
+    if (p.N > 0) {
+        if (p.precision == KMC_FP32_SCREEN) k_finish<true><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
+        else k_finish<false><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RECHECK);
     if (p.N > 0) {

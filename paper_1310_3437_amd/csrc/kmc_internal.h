@@ -44,12 +44,6 @@ struct alignas(16) P64 {
     double x, y, z, vx, vy, vz;
 };
 
-// Per-box, per-step screen thresholds (computed after the sorted copy).
-struct alignas(16) BoxStep {
-    float Tb, Tt, Tc;    // loose reject thresholds for b, -b - dt g2, c2 - D2 g2
-    float vmax;          // bound on |v_k| over the box this step
-};
-
 // Per-context control block in device memory.
 struct Ctl {
     unsigned long long step;            // global index of the next step
@@ -57,10 +51,20 @@ struct Ctl {
     unsigned long long rechecks_total;  // FP32 screen: particles re-searched
     unsigned long long fallbacks_total; // FP32 screen: list overflows
     unsigned long long scratch;         // target of host-requested reductions
+    unsigned long long candidates_total;// candidates recorded by the search (sum over steps)
     unsigned int recheck_count;         // this step's recheck list length
     unsigned int overflow;              // this step's overflow flag
     unsigned int work_next;             // work-queue head of persistent kernels
-    unsigned int pad_[5];
+    unsigned int ovf_count;             // this step's overflow pair list length
+    unsigned int pad_[2];
+};
+
+// FP32 screen thresholds of one box for one step, affine in the pair's g2:
+// reject when b > tb0 + tb1 g2, -b - dt g2 > tt0 + tt1 g2 or
+// (|r|^2 - D2) g2 - b^2 > tc0 + tc1 g2; accept for certain when all three are
+// below minus their bound and g2 > tg0 + tg1 g2.
+struct alignas(16) ScreenBounds {
+    float tb0, tb1, tt0, tt1, tc0, tc1, tg0, tg1;
 };
 
 // Device pointers carved out of the caller's workspace plus launch scalars.
@@ -72,8 +76,8 @@ struct Plan {
     double* A;                     // current state, 6*N SoA (previous cell order)
     P64* B;                        // cell-sorted copy of the current state (records)
     float* vmax_part;              // per scatter block: max |v_k| of its particles this step
-    unsigned int* box_vmax;        // per box: max |v_k| this step (FP32 bits)
-    BoxStep* box_step;             // per box: screen thresholds this step
+    unsigned int* box_vmax;        // per box: max |fl32(v_k)| this step (FP32 bits)
+    ScreenBounds* box_sb;          // per box: FP32 screen thresholds this step
     uint32_t* idA;
     uint32_t* idB;
     uint32_t* cell;                // per particle in A order: global cell
@@ -86,10 +90,13 @@ struct Plan {
     uint32_t* count;               // per cell: particles (zero between steps)
     uint32_t* start;               // per cell + 1: exclusive prefix of count
     uint32_t* partial;             // scan block sums
-    uint32_t* recheck;             // FP32 screen: sorted indices to re-search in FP64
+    uint32_t* recheck;             // sorted indices to re-search in full FP64
+    uint2* ovf;                    // pairs a search lane found beyond its register slots
+    unsigned long long* cand_acc;  // kHistLanes accumulators of recorded candidates
     uint32_t N, C, nboxes, H;
     uint32_t nblk_scan;
     uint32_t recheck_cap;
+    uint32_t ovf_cap;
     uint64_t seed;
     int32_t precision, kinematics, block;
     uint32_t nblk_part;            // scatter blocks (entries of vmax_part)
@@ -97,7 +104,9 @@ struct Plan {
 };
 
 // Kernel launchers (kmc_device.hip).  `ev`, when not null, points to
-// KMC_PHASE_COUNT + 1 events recorded on `s` at the phase boundaries.
+// KMC_PHASE_COUNT + 2 events recorded on `s`: ev[k] at the start of phase k,
+// ev[KMC_PHASE_COUNT] at the end of the step and ev[KMC_PHASE_COUNT + 1]
+// right before the search kernel itself (after the screen's bound kernels).
 hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s);
 hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_read_partners(const Plan& p, int32_t* out, hipStream_t s);

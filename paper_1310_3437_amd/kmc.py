@@ -20,7 +20,7 @@ KMC_FP64, KMC_FP32_SCREEN = 0, 1
 KMC_GEOM_BOX, KMC_GEOM_SPHERE = 0, 1
 KMC_BC_REFLECT, KMC_BC_PERIODIC = 0, 1
 KMC_KIN_AT_TSTAR, KMC_KIN_VEL_ONLY = 0, 1
-PHASES = ("bin", "scan", "scatter", "search", "recheck", "resolve")
+PHASES = ("bin", "scan", "scatter", "search", "finish", "recheck", "resolve")
 
 _lib = None
 
@@ -65,6 +65,8 @@ class KmcStats(C.Structure):
         ("fallbacks", C.c_uint64),
         ("ms", C.c_double * 8),
         ("timed_steps", C.c_uint64),
+        ("search_kernel_ms", C.c_double),
+        ("candidates", C.c_uint64),
     ]
 
 
@@ -228,7 +230,8 @@ class Sim:
         s = KmcStats()
         _check(load().kmc_get_stats(self._ctx, C.byref(s), self._stream()), "kmc_get_stats")
         return dict(steps=s.steps, n_total=s.n_total, cells_total=s.cells_total, rechecks=s.rechecks,
-                    fallbacks=s.fallbacks, timed_steps=s.timed_steps,
+                    fallbacks=s.fallbacks, timed_steps=s.timed_steps, search_kernel_ms=s.search_kernel_ms,
+                    candidates=s.candidates,
                     ms={PHASES[k]: s.ms[k] for k in range(len(PHASES))})
 
     def close(self):

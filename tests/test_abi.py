@@ -33,7 +33,7 @@ def test_struct_sizes_match_header():
     # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 72 bytes
     assert C.sizeof(kmc.KmcBox) == 128
     assert C.sizeof(kmc.KmcConfig) == 72
-    assert C.sizeof(kmc.KmcStats) == 112
+    assert C.sizeof(kmc.KmcStats) == 128
 
 
 def _ws(boxes, **cfg):

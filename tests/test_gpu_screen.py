@@ -5,8 +5,10 @@ Isolated pairs (and triples) are placed so that the FP64 decision sits within
 (d_min = D), the end of the step (t* = dt), the start of the step (t* = 0),
 and near-equal keys of two candidates.  Variants add a large common velocity
 (cancellation in g = v_j - v_i) and coordinates far from the origin.  The
-screen must reproduce the FP64 oracle exactly; with its error bounds switched
-off (guard -1) it must not, which shows the bounds carry the exactness.
+screen must reproduce the FP64 oracle exactly (it drops a pair only when the
+FP64 definition certainly rejects it, and every pair it keeps is decided in
+FP64); with its error bounds switched off (guard -1) it must not, which shows
+the bounds carry the exactness.
 """
 import math
 
@@ -88,14 +90,14 @@ def gpu_vs_oracle(kmc, w, precision, steps=1, **cfg):
 def test_screen_exact_on_adversarial_pairs(kmc, variant):
     w = adversarial(seed=11, **variant)
     print(f"\n[screen] adversarial {variant} N={w.n}", flush=True)
-    ref_acc = 0
-    mism64, st64, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2)
+    mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2)
     assert mism64 == 0 and st64
     mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2)
-    print(f"[screen] mismatches={mism} rechecks={stats['rechecks']}", flush=True)
+    print(f"[screen] mismatches={mism} candidates fp32={stats['candidates']} fp64={s64['candidates']}",
+          flush=True)
     assert mism == 0 and same
-    assert stats["rechecks"] > 0          # the near-boundary cases reach the FP64 recheck
-    del ref_acc
+    # the screen keeps every acceptable pair, and near-boundary rejects too
+    assert stats["candidates"] >= s64["candidates"]
 
 
 def test_negative_control_without_error_bounds(kmc):
@@ -109,11 +111,35 @@ def test_negative_control_without_error_bounds(kmc):
     assert mism_on == 0
 
 
-def test_recheck_overflow_falls_back_to_fp64(kmc):
-    w = adversarial(seed=13)
-    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, recheck_capacity=1, use_graph=True, steps=2)
+def dense_gas(n=20_000, D=0.1, dt=0.05, seed=5):
+    """Uniform gas with many acceptable partners per particle (about 70 at
+    the defaults, about 7 with D=0.05, dt=0.02)."""
+    rng = np.random.default_rng(seed)
+    s = np.empty((6, n))
+    s[0:3] = rng.random((3, n))
+    s[3:6] = rng.standard_normal((3, n))
+    box = I.Box(n=n, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(10, 10, 10), periodic=(True,) * 3, D2=D * D, dt=dt)
+    return I.Workload("dense", [box], s, 2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_candidate_overflow_paths(kmc, precision):
+    prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+    # medium density: lanes overflow their registers and particles their
+    # candidate slots (full re-search), without a whole-step fallback
+    w = dense_gas(D=0.05, dt=0.02)
+    mism, same, stats = gpu_vs_oracle(kmc, w, prec, steps=2)
     assert mism == 0 and same
-    assert stats["fallbacks"] >= 1
+    assert stats["rechecks"] > 0 and stats["fallbacks"] == 0
+    # extreme density: exact by re-search or by the whole-step fallback
+    w = dense_gas()
+    mism, same, stats = gpu_vs_oracle(kmc, w, prec, steps=2)
+    assert mism == 0 and same
+    assert stats["rechecks"] > w.n // 2 or stats["fallbacks"] > 0
+    # a recheck list of one entry forces the fallback every step
+    mism, same, stats = gpu_vs_oracle(kmc, w, prec, recheck_capacity=1, use_graph=True, steps=2)
+    assert mism == 0 and same
+    assert stats["fallbacks"] == 2
 
 
 @pytest.mark.parametrize("guard", [1.0, 16.0])
@@ -123,10 +149,13 @@ def test_guard_scale_does_not_change_results(kmc, guard):
     assert mism == 0 and same
 
 
-def test_screen_rechecks_are_rare_on_a_gas(kmc):
+def test_screen_is_tight_on_a_gas(kmc):
     w = I.c3_sphere(n=400_000, steps=2)
+    _, _, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2)
     mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2)
     assert mism == 0 and same
-    frac = stats["rechecks"] / (2 * w.n)
-    print(f"\n[screen] c3 N=4e5 recheck fraction {frac:.2e}", flush=True)
-    assert frac < 0.01
+    extra = stats["candidates"] / max(s64["candidates"], 1) - 1.0
+    print(f"\n[screen] c3 N=4e5: screen keeps {100 * extra:.3f}% more pairs than FP64 accepts; "
+          f"rechecks {stats['rechecks']}", flush=True)
+    assert 0.0 <= extra < 0.01
+    assert stats["rechecks"] < 0.001 * 2 * w.n
