@@ -217,10 +217,11 @@ def main():
     if "fp64" in results and "fp32" in results:
         line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
     if args.copy_calibration:
-        src = torch.empty(1 << 31, dtype=torch.uint8, device="cuda:0").fill_(1)
+        # an elementwise kernel that reads and writes 2 GiB each
+        src = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         line["copy_calibration_bytes"] = 1 << 31
         del src, dst

@@ -114,13 +114,15 @@ typedef struct kmc_config {
 
 /* Phases timed in profile mode (indices into kmc_stats.ms). */
 enum {
-    KMC_PHASE_BIN = 0,      /* cell index + per-cell count                          */
+    KMC_PHASE_BIN = 0,      /* cell index + per-cell count (runs fused into the
+                               previous step's resolve; 0 ms in practice)           */
     KMC_PHASE_SCAN = 1,     /* exclusive prefix sum of the counts                   */
     KMC_PHASE_SCATTER = 2,  /* cell-sorted copy of the state                        */
     KMC_PHASE_SEARCH = 3,   /* DCA pair search kernel (FP64, or the FP32 screen)    */
     KMC_PHASE_FINISH = 4,   /* closest partner from the recorded candidates         */
     KMC_PHASE_RECHECK = 5,  /* full FP64 re-search of undecided particles           */
-    KMC_PHASE_RESOLVE = 6,  /* mutual check, scatter, free stream, boundaries       */
+    KMC_PHASE_RESOLVE = 6,  /* mutual check, scatter, free stream, boundaries, and
+                               the next step's cell index + count                   */
     KMC_PHASE_COUNT = 7
 };
 

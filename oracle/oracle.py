@@ -69,9 +69,11 @@ def lib():
         L.orc_pair_hash.restype = C.c_uint64
         L.orc_step.argtypes = [bp, dp, u32p, C.c_uint64, i32p, u64p, u64p, C.c_int, u64p]
         L.orc_count_accepted.argtypes = [bp, dp, u32p, C.c_int, u64p, u64p]
+        L.orc_step_sampled.argtypes = [bp, dp, u32p, C.c_uint64, C.POINTER(C.c_int64), C.c_int64, i32p,
+                                       dp, C.c_int]
         L.orc_max_threads.argtypes = []
         for f in ("orc_cell_coords", "orc_pair", "orc_find_partners", "orc_find_partners_bruteforce",
-                  "orc_step", "orc_count_accepted", "orc_max_threads"):
+                  "orc_step", "orc_count_accepted", "orc_step_sampled", "orc_max_threads"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -180,6 +182,26 @@ def direction(seed, step, a):
 
 def pair_hash(a, b):
     return int(lib().orc_pair_hash(int(a), int(b)))
+
+
+def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0):
+    """The oracle step of one box evaluated at the particles `sel` only
+    (indices into the box); `state` is not modified.  Returns (partner
+    indices of the selected particles, their (6, len(sel)) post-step state)."""
+    s = _soa(state)
+    n = s.shape[1]
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    ob = make_box(box, seed=seed, kinematics=kinematics)
+    ob.n = n
+    partner = np.empty(len(sel), dtype=np.int32)
+    out = np.empty((len(sel), 6), dtype=np.float64)
+    rc = lib().orc_step_sampled(C.byref(ob), _ptr(s, C.c_double), _ptr(ids, C.c_uint32), int(step),
+                                _ptr(sel, C.c_int64), len(sel), _ptr(partner, C.c_int32),
+                                _ptr(out, C.c_double), int(nthreads))
+    if rc != 0:
+        raise ValueError(f"orc_step_sampled failed ({rc})")
+    return partner, out.T.copy()
 
 
 def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0):

@@ -174,6 +174,56 @@ int orc_max_threads(void)
 #endif
 }
 
+/* Closest acceptable partner of particle i (index, or -1). */
+static int64_t search_one(const orc_box* b, const double* s, const uint32_t* ids,
+                          const csr_t* t, int64_t i, uint64_t* tests, uint64_t* acc_count)
+{
+    int64_t n = b->n;
+    double pi[6], pj[6];
+    load6(s, n, i, pi);
+    int32_t c[3];
+    orc_cell_coords(b, pi[0], pi[1], pi[2], c);
+    double best_key = INFINITY;
+    uint32_t best_id = UINT32_MAX;
+    int64_t best = -1;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                int32_t d[3] = {dx, dy, dz};
+                int32_t nc[3], wrap[3];
+                int inside = 1;
+                for (int k = 0; k < 3; ++k) {
+                    nc[k] = c[k] + d[k];
+                    wrap[k] = 0;
+                    if (nc[k] < 0) {
+                        if (b->periodic[k]) { nc[k] += b->ncell[k]; wrap[k] = -1; }
+                        else inside = 0;
+                    } else if (nc[k] >= b->ncell[k]) {
+                        if (b->periodic[k]) { nc[k] -= b->ncell[k]; wrap[k] = 1; }
+                        else inside = 0;
+                    }
+                }
+                if (!inside) continue;
+                int64_t cell = linear_cell(b, nc);
+                for (int64_t q = t->start[cell]; q < t->start[cell + 1]; ++q) {
+                    int64_t j = t->member[q];
+                    if (j == i) continue;
+                    ++*tests;
+                    load6(s, n, j, pj);
+                    orc_pair_q pq;
+                    orc_pair(b, pi, pj, wrap, &pq);
+                    if (!pq.acc) continue;
+                    ++*acc_count;
+                    if (better(pq.key, ids[j], best_key, best_id)) {
+                        best_key = pq.key;
+                        best_id = ids[j];
+                        best = j;
+                    }
+                }
+            }
+    return best;
+}
+
 static int64_t search_with_csr(const orc_box* b, const double* s, const uint32_t* ids,
                                const csr_t* t, int32_t* partner, int nthreads,
                                uint64_t* pair_tests, uint64_t* accepted)
@@ -187,49 +237,10 @@ static int64_t search_with_csr(const orc_box* b, const double* s, const uint32_t
     (void)nthreads;
 #endif
     for (int64_t i = 0; i < n; ++i) {
-        double pi[6], pj[6];
-        load6(s, n, i, pi);
-        int32_t c[3];
-        orc_cell_coords(b, pi[0], pi[1], pi[2], c);
-        double best_key = INFINITY;
-        uint32_t best_id = UINT32_MAX;
-        int64_t best = -1;
-        for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    int32_t d[3] = {dx, dy, dz};
-                    int32_t nc[3], wrap[3];
-                    int inside = 1;
-                    for (int k = 0; k < 3; ++k) {
-                        nc[k] = c[k] + d[k];
-                        wrap[k] = 0;
-                        if (nc[k] < 0) {
-                            if (b->periodic[k]) { nc[k] += b->ncell[k]; wrap[k] = -1; }
-                            else inside = 0;
-                        } else if (nc[k] >= b->ncell[k]) {
-                            if (b->periodic[k]) { nc[k] -= b->ncell[k]; wrap[k] = 1; }
-                            else inside = 0;
-                        }
-                    }
-                    if (!inside) continue;
-                    int64_t cell = linear_cell(b, nc);
-                    for (int64_t q = t->start[cell]; q < t->start[cell + 1]; ++q) {
-                        int64_t j = t->member[q];
-                        if (j == i) continue;
-                        ++tests;
-                        load6(s, n, j, pj);
-                        orc_pair_q pq;
-                        orc_pair(b, pi, pj, wrap, &pq);
-                        if (!pq.acc) continue;
-                        ++acc_count;
-                        if (better(pq.key, ids[j], best_key, best_id)) {
-                            best_key = pq.key;
-                            best_id = ids[j];
-                            best = j;
-                        }
-                    }
-                }
-        partner[i] = (int32_t)best;
+        uint64_t nt_i = 0, na_i = 0;
+        partner[i] = (int32_t)search_one(b, s, ids, t, i, &nt_i, &na_i);
+        tests += nt_i;
+        acc_count += na_i;
     }
     if (pair_tests) *pair_tests = tests;
     if (accepted) *accepted = acc_count;
@@ -426,6 +437,58 @@ static void apply_bc(const orc_box* b, double x[3], double v[3])
 /* One step (Section 1: search, mutual collisions, update, boundaries)       */
 /* ------------------------------------------------------------------------ */
 
+/* Collision of the mutual pair (a, c) with ids[a] < ids[c]: collision time
+ * t* (from a's side) and the two new velocities.  Elastic, isotropic scatter
+ * of equal masses in the centre-of-mass frame: |g| is kept, its direction is
+ * drawn uniformly with the random numbers of the pair's smaller id. */
+static void collide_pair(const orc_box* b, const double* s, const uint32_t* ids,
+                         uint64_t step, int64_t a, int64_t c,
+                         double nva[3], double nvc[3], double* tstar)
+{
+    int64_t n = b->n;
+    double pa[6], pc[6];
+    load6(s, n, a, pa);
+    load6(s, n, c, pc);
+    int32_t ca[3], cc[3], wrap[3];
+    orc_cell_coords(b, pa[0], pa[1], pa[2], ca);
+    orc_cell_coords(b, pc[0], pc[1], pc[2], cc);
+    for (int k = 0; k < 3; ++k) axis_adjacent(b, k, ca[k], cc[k], &wrap[k]);
+    orc_pair_q q;
+    orc_pair(b, pa, pc, wrap, &q);
+    *tstar = (-q.b) / q.g2;
+    double nhat[3];
+    orc_direction(b->seed, step, ids[a], nhat);
+    double hg = 0.5 * sqrt(q.g2);
+    for (int k = 0; k < 3; ++k) {
+        double vcm = 0.5 * (pa[3 + k] + pc[3 + k]);
+        nva[k] = vcm + hg * nhat[k];
+        nvc[k] = vcm - hg * nhat[k];
+    }
+}
+
+/* Free flight of one particle over the step, then the boundary conditions.
+ * A collider (hit) moves to t* with its old velocity and on with the new one
+ * (or, in velocity-only mode, the whole step with the new one). */
+static void advance_one(const orc_box* b, double x[3], double v[3], int hit,
+                        const double vn[3], double tstar)
+{
+    const double dt = b->dt;
+    if (hit) {
+        for (int k = 0; k < 3; ++k) {
+            if (b->kinematics == 0) {
+                double xs = x[k] + v[k] * tstar;
+                x[k] = xs + vn[k] * (dt - tstar);
+            } else {
+                x[k] = x[k] + vn[k] * dt;
+            }
+            v[k] = vn[k];
+        }
+    } else {
+        for (int k = 0; k < 3; ++k) x[k] = x[k] + v[k] * dt;
+    }
+    apply_bc(b, x, v);
+}
+
 int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
              int32_t* partner_out, uint64_t* npairs, uint64_t* digest,
              int nthreads, uint64_t* pair_tests)
@@ -461,26 +524,11 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
         int32_t p = partner[i];
         if (p < 0 || partner[p] != (int32_t)i || !(ids[i] < ids[p])) continue;
         int64_t a = i, c = p;
-        double pa[6], pc[6];
-        load6(s, n, a, pa);
-        load6(s, n, c, pc);
-        int32_t ca[3], cc[3], wrap[3];
-        orc_cell_coords(b, pa[0], pa[1], pa[2], ca);
-        orc_cell_coords(b, pc[0], pc[1], pc[2], cc);
-        for (int k = 0; k < 3; ++k) axis_adjacent(b, k, ca[k], cc[k], &wrap[k]);
-        orc_pair_q q;
-        orc_pair(b, pa, pc, wrap, &q);
-        /* collision time of the pair, oriented from a to c */
-        double tstar = (-q.b) / q.g2;
-        /* elastic, isotropic scatter of equal masses in the centre-of-mass
-         * frame: |g| is kept, its direction is drawn uniformly */
-        double nhat[3];
-        orc_direction(b->seed, step, ids[a], nhat);
-        double hg = 0.5 * sqrt(q.g2);
+        double nva[3], nvc[3], tstar;
+        collide_pair(b, s, ids, step, a, c, nva, nvc, &tstar);
         for (int k = 0; k < 3; ++k) {
-            double vcm = 0.5 * (pa[3 + k] + pc[3 + k]);
-            nv[(size_t)k * nn + (size_t)a] = vcm + hg * nhat[k];
-            nv[(size_t)k * nn + (size_t)c] = vcm - hg * nhat[k];
+            nv[(size_t)k * nn + (size_t)a] = nva[k];
+            nv[(size_t)k * nn + (size_t)c] = nvc[k];
         }
         ts[a] = tstar;
         ts[c] = tstar;
@@ -490,31 +538,15 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
         dig += orc_pair_hash(ids[a], ids[c]);
     }
 
-    /* 4: free streaming; colliders move to t* with the old velocity and on
-     * with the new one (or, in velocity-only mode, the whole step with the
-     * new one); then the boundary conditions */
-    const double dt = b->dt;
+    /* 4: free streaming and boundary conditions */
     for (int64_t i = 0; i < n; ++i) {
-        double x[3], v[3];
+        double x[3], v[3], vn[3];
         for (int k = 0; k < 3; ++k) {
             x[k] = s[(size_t)k * nn + (size_t)i];
             v[k] = s[(size_t)(3 + k) * nn + (size_t)i];
+            vn[k] = nv[(size_t)k * nn + (size_t)i];
         }
-        if (hit[i]) {
-            for (int k = 0; k < 3; ++k) {
-                double vn = nv[(size_t)k * nn + (size_t)i];
-                if (b->kinematics == 0) {
-                    double xs = x[k] + v[k] * ts[i];
-                    x[k] = xs + vn * (dt - ts[i]);
-                } else {
-                    x[k] = x[k] + vn * dt;
-                }
-                v[k] = vn;
-            }
-        } else {
-            for (int k = 0; k < 3; ++k) x[k] = x[k] + v[k] * dt;
-        }
-        apply_bc(b, x, v);
+        advance_one(b, x, v, hit[i], vn, ts[i]);
         for (int k = 0; k < 3; ++k) {
             s[(size_t)k * nn + (size_t)i] = x[k];
             s[(size_t)(3 + k) * nn + (size_t)i] = v[k];
@@ -527,5 +559,60 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
     free(nv);
     free(ts);
     free(hit);
+    return 0;
+}
+
+/* The same step evaluated for selected particles only: for each listed index
+ * sel[k], its partner (index or -1) and its state after the step.  The bins
+ * are built for all particles; the search runs for each selected particle and
+ * for its partner (to decide mutuality), so large runs can be checked at
+ * sampled particles. */
+int orc_step_sampled(const orc_box* b, const double* s, const uint32_t* ids, uint64_t step,
+                     const int64_t* sel, int64_t nsel, int32_t* partner_out,
+                     double* state_out, int nthreads)
+{
+    if (!box_ok(b) || (b->n > 0 && (!s || !ids)) || nsel < 0 ||
+        (nsel > 0 && (!sel || !partner_out || !state_out)))
+        return -1;
+    if (b->n > INT32_MAX) return -1;
+    for (int64_t k = 0; k < nsel; ++k)
+        if (sel[k] < 0 || sel[k] >= b->n) return -1;
+    int64_t n = b->n;
+    csr_t t;
+    if (build_csr(b, s, &t) != 0) return -2;
+#ifdef _OPENMP
+    int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+#else
+    (void)nthreads;
+#endif
+    for (int64_t k = 0; k < nsel; ++k) {
+        int64_t i = sel[k];
+        uint64_t tests = 0, acc = 0;
+        int64_t p = search_one(b, s, ids, &t, i, &tests, &acc);
+        int hit = p >= 0 && search_one(b, s, ids, &t, p, &tests, &acc) == i;
+        double x[3], v[3], vn[3] = {0.0, 0.0, 0.0}, tstar = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            x[a] = s[(int64_t)a * n + i];
+            v[a] = s[(int64_t)(3 + a) * n + i];
+        }
+        if (hit) {
+            double nva[3], nvc[3];
+            if (ids[i] < ids[p]) {
+                collide_pair(b, s, ids, step, i, p, nva, nvc, &tstar);
+                for (int a = 0; a < 3; ++a) vn[a] = nva[a];
+            } else {
+                collide_pair(b, s, ids, step, p, i, nva, nvc, &tstar);
+                for (int a = 0; a < 3; ++a) vn[a] = nvc[a];
+            }
+        }
+        advance_one(b, x, v, hit, vn, tstar);
+        partner_out[k] = (int32_t)p;
+        for (int a = 0; a < 3; ++a) {
+            state_out[6 * k + a] = x[a];
+            state_out[6 * k + 3 + a] = v[a];
+        }
+    }
+    free_csr(&t);
     return 0;
 }

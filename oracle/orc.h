@@ -99,6 +99,14 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
              int32_t* partner, uint64_t* npairs, uint64_t* digest,
              int nthreads, uint64_t* pair_tests);
 
+/* The step of orc_step evaluated at selected particles only (checks of runs
+ * too large for a full oracle step): for k < nsel, partner_out[k] receives
+ * the partner (index or -1) of particle sel[k] and state_out[6k .. 6k+6) its
+ * x, y, z, vx, vy, vz after the step.  s is not modified. */
+int orc_step_sampled(const orc_box* b, const double* s, const uint32_t* ids, uint64_t step,
+                     const int64_t* sel, int64_t nsel, int32_t* partner_out,
+                     double* state_out, int nthreads);
+
 /* Ordered pairs (i, j != i) examined and ordered pairs accepted by the
  * partner criteria in the current state, without choosing partners; used by
  * the collision-rate check. */

@@ -116,6 +116,19 @@ __device__ __forceinline__ uint64_t pair_hash(uint32_t a, uint32_t b)
     return z ^ (z >> 31);
 }
 
+// Logical block index for kernels whose neighbouring blocks share data:
+// the dispatcher hands consecutive workgroups to the 8 XCDs in turn, each
+// with its own L2, so block b is mapped to a contiguous per-XCD range of
+// tiles (a bijection for any grid size) and each XCD sweeps one slice of
+// the cell-sorted particles.
+constexpr uint32_t kXcds = 8;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb)
+{
+    const uint32_t x = b % kXcds, idx = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x * q + (x < r ? x : r) + idx;
+}
+
 __device__ __forceinline__ const BoxDev& box_of(const Plan& p, uint32_t i)
 {
     return p.boxes[p.boxidx ? p.boxidx[i] : 0u];
@@ -237,23 +250,21 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
 // inside its cell; the order inside a cell never affects a result.
 // --------------------------------------------------------------------------
 
-__global__ void k_bin(Plan p)
+// Cell of particle i at position (x, y, z) and its slot: the state is in
+// the previous step's cell order, so neighbouring lanes mostly share a cell
+// and each run of equal cells takes its slots with one atomic issued by the
+// run's first lane.  Every lane of the wave must call this.
+__device__ __forceinline__ void bin_particle(const Plan& p, uint32_t i, bool valid, const BoxDev& B, double x,
+                                             double y, double z)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool valid = i < p.N;
     uint32_t c = 0xFFFFFFFFu;
     if (valid) {
-        const BoxDev& B = box_of(p, i);
-        const size_t N = p.N;
-        const int cx = cell1(p.A[i], B.lo[0], B.inv_h[0], B.nc[0]);
-        const int cy = cell1(p.A[N + i], B.lo[1], B.inv_h[1], B.nc[1]);
-        const int cz = cell1(p.A[2 * N + i], B.lo[2], B.inv_h[2], B.nc[2]);
+        const int cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
+        const int cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
+        const int cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
         c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
         p.cell[i] = c;
     }
-    // The state is still in the previous step's cell order, so neighbouring
-    // lanes mostly share a cell: each run of equal cells takes its slots
-    // with one atomic issued by the run's first lane.
     const int lane = threadIdx.x & 63;
     const uint64_t live = __ballot(valid);
     if (live == 0) return;
@@ -269,6 +280,16 @@ __global__ void k_bin(Plan p)
     if (head) base = atomicAdd(&p.count[c], (unsigned int)(next - lane));
     base = (uint32_t)__shfl((int)base, my_head, 64);
     if (valid) p.slot[i] = base + (uint32_t)(lane - my_head);
+}
+
+// a1 for the state written by kmc_init (later steps bin in k_resolve).
+__global__ void k_bin(Plan p)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool valid = i < p.N;
+    const size_t N = p.N;
+    const BoxDev& B = box_of(p, valid ? i : 0u);
+    bin_particle(p, i, valid, B, valid ? p.A[i] : 0.0, valid ? p.A[N + i] : 0.0, valid ? p.A[2 * N + i] : 0.0);
 }
 
 // --------------------------------------------------------------------------
@@ -777,7 +798,7 @@ void k_search_half(Plan p)
 {
     __shared__ typename Pol::Lds lds;
     const int lane = threadIdx.x;
-    const uint32_t i = blockIdx.x * 64u + (uint32_t)lane;
+    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * 64u + (uint32_t)lane;
     const bool valid = i < p.N;
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
@@ -1005,6 +1026,7 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
     __shared__ uint64_t lds[32];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t my_np = 0, my_dig = 0;
+    double nx = 0.0, ny = 0.0, nz = 0.0;
     if (i < p.N) {
         const BoxDev& B = box_of(p, i);
         const size_t N = p.N;
@@ -1072,7 +1094,10 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
             p.A[(3 + k) * N + i] = v[k];
         }
         p.idA[i] = id;
+        nx = x[0]; ny = x[1]; nz = x[2];
     }
+    // a1 of the next step: cell and slot of the new position
+    bin_particle(p, i, i < p.N, box_of(p, i < p.N ? i : 0u), nx, ny, nz);
     block_sum2(my_np, my_dig, lds);
     if (threadIdx.x == 0 && my_np != 0) {
         const size_t row = (size_t)(p.ctl->steps_done % p.H) * kHistLanes + (blockIdx.x % kHistLanes);
@@ -1135,6 +1160,7 @@ hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s)
     k_fill_u32<<<blocks_for(p.C, b) < 4096 ? blocks_for(p.C, b) : 4096, b, 0, s>>>(p.count, p.C, 0u);
     if (p.N > 0) k_fill_u32<<<4096, b, 0, s>>>(p.sl_cnt, (size_t)p.N, 0u);
     k_init_ctl<<<1, 64, 0, s>>>(p, 0);
+    if (p.N > 0) k_bin<<<blocks_for(p.N, b), b, 0, s>>>(p);
     return hipGetLastError();
 }
 
@@ -1143,8 +1169,7 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     const uint32_t b = (uint32_t)p.block;
     const uint32_t gN = blocks_for(p.N, b);
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
-    mark(KMC_PHASE_BIN);
-    if (p.N > 0) k_bin<<<gN, b, 0, s>>>(p);
+    mark(KMC_PHASE_BIN);   // binning runs at the end of the previous step (k_resolve) or in kmc_init
     mark(KMC_PHASE_SCAN);
     k_scan_reduce<<<p.nblk_scan, kScanBlock, 0, s>>>(p);
     k_scan_partials<<<1, 1024, 0, s>>>(p);
@@ -1173,8 +1198,8 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     }
     mark(KMC_PHASE_RECHECK);
     if (p.N > 0) {
-        k_recheck64<<<512, 256, 0, s>>>(p);
-        k_fallback64<<<2048, 256, 0, s>>>(p);
+        k_recheck64<<<128, 256, 0, s>>>(p);
+        k_fallback64<<<512, 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RESOLVE);
     if (p.N > 0) k_resolve<<<gN, b, 0, s>>>(p);

@@ -1,0 +1,145 @@
+"""GPU parity at the workloads' full sizes.
+
+* c3_sphere at N = 1e8 (the headline workload) runs in the launch
+  configuration the benchmark times (per-phase events on the launch stream,
+  no graph, default block size).  A full oracle step at this size takes
+  minutes, so the oracle evaluates the same step at sampled particles (random
+  ones, colliders, chosen-but-not-mutual ones, particles at the sphere wall)
+  and must give the same partners and post-step states bit for bit.  Over all
+  particles: the collision count and digest the library reports equal those
+  of its partner array, and the FP64 and FP32-screen paths give identical
+  partner arrays and states.
+* c2_shock (N = 1e6, 19.5 M cells) and c4_batch (256 boxes, ~5e6 particles)
+  are compared with full oracle steps.
+* c5_blobs (N = 1e7, ~3e10 pair tests per step) is checked at sampled
+  particles, both precisions.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1310_3437_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+def pair_hash_np(a, b):
+    """SplitMix64 finaliser of ((a << 32) | b) + golden gamma, vectorised;
+    checked against the oracle's pair hash on a few pairs before use."""
+    with np.errstate(over="ignore"):
+        z = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def mutual_pairs(p):
+    """Colliding pairs (a < b) of a partner array (index = id)."""
+    n = p.shape[0]
+    idx = np.arange(n, dtype=np.int64)
+    has = p >= 0
+    mutual = np.zeros(n, dtype=bool)
+    pi = p[has].astype(np.int64)
+    mutual[has] = p[pi] == idx[has]
+    a = idx[mutual & (idx < p)]
+    return a, p[a].astype(np.int64), mutual
+
+
+def run_sampled(kmc, w, precision, nsample, seed=0, wall_band=None, **cfg):
+    """One GPU step of a single-box workload, checked over all particles by
+    properties and at sampled particles against the oracle's per-particle
+    evaluation.  Returns (partner array, state) of the GPU run."""
+    import torch
+    assert len(w.boxes) == 1
+    box = w.boxes[0]
+    n = w.n
+    print(f"\n[full] {w.name} N={n} precision={precision} cfg={cfg}", flush=True)
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics,
+                  precision=precision, **cfg)
+    sim.step(1)
+    p = sim.partners().cpu().numpy()
+    st = sim.state()
+    hn, hd = sim.history()
+    stats = sim.stats()
+    sim.close()
+
+    a, b, mutual = mutual_pairs(p)
+    assert int(hn[-1]) == a.size
+    for k in range(0, a.size, max(1, a.size // 7)):
+        assert int(pair_hash_np(a[k:k + 1], b[k:k + 1])[0]) == O.pair_hash(int(a[k]), int(b[k]))
+    assert int(pair_hash_np(a, b).sum(dtype=np.uint64)) == int(hd[-1])
+    print(f"[full] pairs={a.size} rechecks={stats['rechecks']} fallbacks={stats['fallbacks']}", flush=True)
+
+    rng = np.random.default_rng(seed)
+    parts = [rng.choice(n, nsample, replace=False),
+             rng.choice(np.flatnonzero(mutual), min(nsample // 2, int(mutual.sum())), replace=False),
+             np.flatnonzero((p >= 0) & ~mutual)[:nsample // 4], np.array([0, n - 1])]
+    if wall_band is not None:
+        parts.append(np.flatnonzero(wall_band(w.state))[:nsample // 4])
+    sel = np.unique(np.concatenate(parts)).astype(np.int64)
+    got = st[:, torch.as_tensor(sel, device=st.device)].cpu().numpy()
+    ref_p, ref_s = O.step_sampled(box, w.state, np.arange(n, dtype=np.uint32), 0, sel,
+                                  seed=w.seed, kinematics=w.kinematics)
+    bad = np.flatnonzero(p[sel] != ref_p)
+    assert bad.size == 0, f"{bad.size} of {sel.size} sampled partners differ, first ids {sel[bad[:5]]}"
+    assert np.array_equal(got, ref_s), "sampled post-step states differ"
+    print(f"[full] {sel.size} sampled particles identical", flush=True)
+    return p, st
+
+
+@pytest.mark.timeout(600)
+def test_c3_sphere_1e8_sampled_and_paths_identical(kmc):
+    w = I.c3_sphere(n=100_000_000, steps=1)
+    h = w.boxes[0].h[0]
+
+    def near_wall(s):
+        r2 = s[0] * s[0] + s[1] * s[1] + s[2] * s[2]
+        return r2 > (1.0 - 2.0 * h) ** 2
+
+    # the benchmark's launch configuration
+    bench_cfg = dict(history=64, profile=True)
+    p32, s32 = run_sampled(kmc, w, kmc.KMC_FP32_SCREEN, 3000, seed=1, wall_band=near_wall, **bench_cfg)
+    p64, s64 = run_sampled(kmc, w, kmc.KMC_FP64, 1000, seed=2, **bench_cfg)
+    assert np.array_equal(p32, p64), "FP32-screen and FP64 partner arrays differ"
+    assert bool((s32 == s64).all().item()), "FP32-screen and FP64 states differ"
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c5_blobs_1e7_sampled(kmc, precision):
+    w = I.c5_blobs(steps=1)
+    prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+    run_sampled(kmc, w, prec, 2000, seed=5)
+
+
+def full_oracle(kmc, w, steps, precision):
+    print(f"\n[full] {w.name} N={w.n} boxes={len(w.boxes)} steps={steps} {precision}", flush=True)
+    prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics, precision=prec)
+    ref = O.Run(w)
+    hist = []
+    for s in range(steps):
+        sim.step(1)
+        hist.append(ref.step())
+        p = sim.partners().cpu().numpy()
+        bad = np.flatnonzero(p != ref.partner_by_id)
+        assert bad.size == 0, f"step {s}: {bad.size} partner mismatches, first ids {bad[:5]}"
+    hn, hd = sim.history()
+    assert [(int(x), int(y)) for x, y in zip(hn, hd)][-steps:] == hist
+    assert np.array_equal(sim.state().cpu().numpy(), ref.full_state())
+    sim.close()
+    print(f"[full] ok, pairs per step {[h[0] for h in hist]}", flush=True)
+
+
+@pytest.mark.timeout(600)
+def test_c2_shock_1e6_full_oracle(kmc):
+    full_oracle(kmc, I.c2_shock(steps=3), 3, "fp32")
+
+
+@pytest.mark.timeout(600)
+def test_c4_batch_256_boxes_full_oracle(kmc):
+    full_oracle(kmc, I.c4_batch(steps=2), 2, "fp32")

@@ -461,3 +461,25 @@ def test_resume_is_exact():
     dig_b += [c.step() for _ in range(3)]
     assert dig_a == dig_b
     assert np.array_equal(a.full_state(), c.full_state())
+
+
+@pytest.mark.parametrize("name", ["c1_small", "c2_shock", "c3_sphere", "c5_blobs"])
+def test_sampled_step_equals_full_step(name):
+    """The per-particle evaluation used to check runs too large for a full
+    oracle step gives exactly the full step's partners and states."""
+    small = dict(c1_small={}, c2_shock=dict(n=20_000), c3_sphere=dict(n=30_000), c5_blobs=dict(n=20_000))
+    w = getattr(I, name)(steps=1, **small[name])
+    box = w.boxes[0]
+    n = box.n
+    ids = np.arange(n, dtype=np.uint32)
+    s0 = np.array(w.state[:, :n], order="C")
+    s1 = s0.copy()
+    part, npairs, _, _ = O.step_box(box, s1, ids, 7, seed=w.seed, kinematics=w.kinematics)
+    assert npairs > 0
+    rng = np.random.default_rng(3)
+    sel = np.concatenate([rng.choice(n, 300, replace=False), np.flatnonzero(part >= 0)[:300], [0, n - 1]])
+    ps, st = O.step_sampled(box, s0, ids, 7, sel, seed=w.seed, kinematics=w.kinematics)
+    assert np.array_equal(ps, part[sel])
+    assert np.array_equal(st, s1[:, sel])
+    with pytest.raises(ValueError):
+        O.step_sampled(box, s0, ids, 7, np.array([n]), seed=w.seed)
