@@ -14,6 +14,10 @@ dominant kernel (the partner search).  `cpu_baseline` times the CPU oracle
 (test infrastructure) on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
+                    [--workload c3_sphere|c2_shock|c4_batch|c5_blobs] [--dt-rule adaptive]
+
+The other workloads (shock tube, 256-box batch, Gaussian blobs) print the same
+line for their own configuration; the headline is c3_sphere.
 """
 import argparse
 import hashlib
@@ -66,12 +70,13 @@ def traffic_for(path_name, launches_bytes):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def run_path(kmc, w, precision, steps, warmup, pair_tests):
+def run_path(kmc, w, precision, steps, warmup, pair_tests, search_mode=0):
     import torch
     name = "fp64" if precision == kmc.KMC_FP64 else "fp32_screen"
     log(f"[bench] {name}: init N={w.n}")
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=precision,
-                  history=max(64, steps + warmup), profile=True)
+                  history=max(64, steps + warmup), profile=True, dt_rule=w.dt_rule,
+                  dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search_mode)
     sim.step(warmup)
     torch.cuda.synchronize()
     s0 = sim.stats()
@@ -104,20 +109,61 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests):
     return out
 
 
-def cpu_baseline(n_sample):
-    from oracle import oracle as O
+def workload(name, n, dt_rule):
     from paper_1310_3437_amd import inputs
-    log(f"[bench] cpu baseline: oracle step on the c3_sphere recipe at N={n_sample}")
-    w = inputs.c3_sphere(n=n_sample, steps=1)
+    if name == "c3_sphere":
+        w = inputs.c3_sphere(n=n)
+        b = w.boxes[0]
+        desc = (f"c3_sphere: N={n:.0e} uniform ball R=1, v=-0.5x+N(0,0.1^2), reflecting sphere, "
+                f"{b.ncell[0]}^3 cells (edge {b.h[0]:.5f} >= D={w.info['D']:.5f}), dt={b.dt:.4e}")
+    elif name == "c2_shock":
+        w = inputs.c2_shock(n=n)
+        b = w.boxes[0]
+        desc = (f"c2_shock: N={n:.0e} tube 1x0.1x0.1, reflecting walls, 8/9 of N left (sigma_v 1), "
+                f"1/9 right (sigma_v 0.35), {b.ncell[0]}x{b.ncell[1]}x{b.ncell[2]} cells, dt={b.dt:.4e}")
+    elif name == "c4_batch":
+        w = inputs.c4_batch()
+        desc = (f"c4_batch: {len(w.boxes)} periodic boxes, N_b log-uniform in [1e3, 1e5] "
+                f"(total {w.n}), ~3 particles per cell, one launch per phase for all boxes")
+    elif name == "c5_blobs":
+        w = inputs.c5_blobs(n=n)
+        b = w.boxes[0]
+        desc = (f"c5_blobs: N={n:.0e} in 64 Gaussian blobs, periodic unit cube, D={w.info['D']:.2e}, "
+                f"{b.ncell[0]}^3 cells, dt={b.dt:.4e}")
+    else:
+        raise SystemExit(f"bench.py: unknown workload {name}")
+    if dt_rule == "adaptive":
+        import dataclasses
+        w.boxes = [dataclasses.replace(b, dt=10.0 * b.dt) for b in w.boxes]
+        w.dt_rule = 1
+        desc += "; adaptive dt = dx / v_max (cap 10x the fixed dt)"
+    return w, desc
+
+
+def cpu_workload(name, n_sample):
+    from paper_1310_3437_amd import inputs
+    if name == "c3_sphere":
+        return inputs.c3_sphere(n=n_sample, steps=1), f"the c3_sphere recipe at N={n_sample:.0e} (same density law)"
+    if name == "c2_shock":
+        return inputs.c2_shock(n=n_sample, steps=1), f"the c2_shock recipe at N={n_sample:.0e}"
+    if name == "c4_batch":
+        return inputs.c4_batch(nboxes=64, steps=1), "the first 64 boxes of the c4_batch recipe"
+    return inputs.c5_blobs(n=n_sample, steps=1), f"the c5_blobs recipe at N={n_sample:.0e} (same particles per cell)"
+
+
+def cpu_baseline(name, n_sample):
+    from oracle import oracle as O
+    w, what = cpu_workload(name, n_sample)
+    log(f"[bench] cpu baseline: oracle step on {what}")
     r = O.Run(w)
+    n_sample = w.n
     nt = O.lib().orc_max_threads()
     t0 = time.perf_counter()
     r.step()
     el = time.perf_counter() - t0
     return dict(value=n_sample / el, unit="particle-steps/s", cores=int(nt), kind="oracle",
                 sample=f"one oracle step (search with {nt} OpenMP threads, serial bin/resolve/stream) "
-                       f"of the c3_sphere recipe at N={n_sample:.0e} (same density law, ~3 particles "
-                       f"per cell), {el:.1f} s; {r.pair_tests / el:.3e} pair-tests/s",
+                       f"of {what}, {el:.1f} s; {r.pair_tests / el:.3e} pair-tests/s",
                 pair_tests_per_s=r.pair_tests / el, seconds=el,
                 cpu=platform.processor() or platform.machine())
 
@@ -127,9 +173,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=float, default=1e8)
+    ap.add_argument("--workload", default="c3_sphere")
+    ap.add_argument("--n", type=float, default=None, help="particles (default: the workload's full size)")
+    ap.add_argument("--dt-rule", default="fixed", choices=("fixed", "adaptive"))
+    ap.add_argument("--search", default="half", choices=("half", "full"),
+                    help="partner-search organisation (the result is the same)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=float, default=1e7)
+    ap.add_argument("--cpu-sample", type=float, default=None)
     ap.add_argument("--paths", default="fp64,fp32")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
@@ -144,11 +194,15 @@ def main():
     kmc.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
-    n = int(args.n)
+    full = dict(c3_sphere=1e8, c2_shock=1e6, c4_batch=None, c5_blobs=1e7)
+    sample = dict(c3_sphere=1e7, c2_shock=1e6, c4_batch=None, c5_blobs=3e5)
+    if args.workload not in full:
+        raise SystemExit(f"bench.py: unknown workload {args.workload}")
+    n_arg = args.n if args.n is not None else full[args.workload]
     t0 = time.perf_counter()
-    w = inputs.c3_sphere(n=n)
-    log(f"[bench] generated c3_sphere N={n} in {time.perf_counter() - t0:.1f} s; "
-        f"cells {w.boxes[0].ncell}, dt {w.boxes[0].dt:.4e}")
+    w, desc = workload(args.workload, int(n_arg) if n_arg else None, args.dt_rule)
+    n = w.n
+    log(f"[bench] generated {args.workload} N={n} in {time.perf_counter() - t0:.1f} s")
 
     results = {}
     pair_tests = None
@@ -157,7 +211,8 @@ def main():
         prec = kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
         if name == "fp32" and not have_f32:
             continue
-        r = run_path(kmc, w, prec, args.steps, args.warmup, pair_tests)
+        r = run_path(kmc, w, prec, args.steps, args.warmup, pair_tests,
+                     kmc.KMC_SEARCH_FULL if args.search == "full" else kmc.KMC_SEARCH_HALF)
         pair_tests = r["pair_tests"]
         results[name] = r
 
@@ -167,11 +222,18 @@ def main():
     head = results.get("fp32") or results["fp64"]
     head_name = "fp32_screen" if "fp32" in results else "fp64"
     search_ms = head["search_kernel_ms"]
-    flops = FLOP_PER_PAIR_EVAL * head["pair_tests"] / 2
+    # the half-neighbourhood search evaluates each unordered pair once, the
+    # full one each ordered pair
+    evals = head["pair_tests"] // 2 if args.search == "half" else head["pair_tests"]
+    flops = FLOP_PER_PAIR_EVAL * evals
     achieved = flops / (search_ms * 1e-3) / 1e12
-    traffic = traffic_for(head_name, None)
+    headline = (args.workload == "c3_sphere" and n == 100_000_000 and args.dt_rule == "fixed"
+                and args.search == "half")
+    traffic = traffic_for(head_name, None) if headline else None
+    metric = METRIC if args.workload == "c3_sphere" and n == 100_000_000 else \
+        f"particle-steps/s on {args.workload} (FP32-screen vs plain FP64, identical pair lists)"
     line = {
-        "metric": METRIC,
+        "metric": metric,
         "value": head["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -184,14 +246,13 @@ def main():
         "dtype": "f32+f64" if head_name == "fp32_screen" else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"c3_sphere: N={n:.0e} uniform ball R=1, v=-0.5x+N(0,0.1^2), reflecting sphere, "
-                        f"{w.boxes[0].ncell[0]}^3 cells (edge {w.boxes[0].h[0]:.5f} >= D={w.info['D']:.5f}), "
-                        f"dt={w.boxes[0].dt:.4e}",
+            "workload": desc,
             "N": n,
             "path": head_name,
         },
         "roofline": {
-            "kernel": "k_search_half<" + ("PolF32> (FP32 screen)" if head_name == "fp32_screen" else "PolF64> (FP64)"),
+            "kernel": f"k_search_{args.search}<" + ("PolF32> (FP32 screen)" if head_name == "fp32_screen"
+                                                   else "PolF64> (FP64)"),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_VALU_TFLOPS,
@@ -199,7 +260,7 @@ def main():
             "frac": achieved / PEAK_VALU_TFLOPS,
             "traffic": traffic,
             "flop_per_pair_eval": FLOP_PER_PAIR_EVAL,
-            "pair_evals_per_launch": head["pair_tests"] // 2,
+            "pair_evals_per_launch": evals,
             "avg_launch_ms": search_ms,
         },
         "roofline_step": {
@@ -226,7 +287,8 @@ def main():
         line["copy_calibration_bytes"] = 1 << 31
         del src, dst
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(int(args.cpu_sample))
+        cs = args.cpu_sample if args.cpu_sample is not None else sample[args.workload]
+        line["cpu_baseline"] = cpu_baseline(args.workload, int(cs) if cs else None)
     print(json.dumps(line), flush=True)
 
 

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define KMC_ABI_VERSION 1
+#define KMC_ABI_VERSION 2
 
 typedef enum {
     KMC_OK = 0,
@@ -61,6 +61,16 @@ typedef enum { KMC_FP64 = 0, KMC_FP32_SCREEN = 1 } kmc_precision;
 typedef enum { KMC_GEOM_BOX = 0, KMC_GEOM_SPHERE = 1 } kmc_geometry;
 typedef enum { KMC_BC_REFLECT = 0, KMC_BC_PERIODIC = 1 } kmc_bc;
 typedef enum { KMC_KIN_AT_TSTAR = 0, KMC_KIN_VEL_ONLY = 1 } kmc_kinematics;
+typedef enum { KMC_DT_FIXED = 0, KMC_DT_ADAPTIVE = 1 } kmc_dt_rule;
+/* How the partner search is organised (the result is the same):
+ *   KMC_SEARCH_HALF  every unordered neighbour pair is tested once and
+ *                    acceptable pairs are recorded for both particles; the
+ *                    partner is the minimum over the recorded pairs (fast
+ *                    when particles have few acceptable partners);
+ *   KMC_SEARCH_FULL  every particle scans its whole neighbourhood keeping
+ *                    a running minimum (twice the pair tests, no lists; for
+ *                    dense cells with many acceptable partners). */
+typedef enum { KMC_SEARCH_HALF = 0, KMC_SEARCH_FULL = 1 } kmc_search_mode;
 
 /* One independent simulation box.
  *   n         particles in the box (their state is a contiguous slice of the
@@ -75,7 +85,7 @@ typedef enum { KMC_KIN_AT_TSTAR = 0, KMC_KIN_VEL_ONLY = 1 } kmc_kinematics;
  *             cell of x is clamp(floor((x - lo) * inv_h), 0, ncell - 1));
  *             the cell edge 1/inv_h must be >= sqrt(D2) on every axis;
  *   D2        squared interaction diameter sigma/pi (> 0);
- *   dt        time step (> 0).
+ *   dt        time step (> 0); with KMC_DT_ADAPTIVE the largest step allowed.
  * Requirement (not checked): no particle moves more than one box length per
  * step. */
 typedef struct kmc_box {
@@ -106,18 +116,39 @@ typedef struct kmc_config {
     int32_t use_graph;         /* 1: each step is replayed from a captured hipGraph      */
     int32_t block_size;        /* threads per block, multiple of 64 in [64, 1024]; 0 = 256 */
     int32_t profile;           /* 1: time every phase with HIP events (disables graphs)  */
-    int32_t reserved[5];       /* must be zero                                           */
+    int32_t dt_rule;           /* kmc_dt_rule (see below)                                */
+    int32_t search_mode;       /* kmc_search_mode                                        */
+    int32_t reserved[3];       /* must be zero                                           */
     double guard_scale;        /* FP32 screen: factor applied to the derived rounding-error
                                   bounds; 0 = 4 (default), >= 1 otherwise.  -1 disables the
                                   bounds (testing only: the screen is then not exact)     */
+    double dt_factor;          /* KMC_DT_ADAPTIVE: the factor C below; 0 = 1 (the paper's
+                                  rule), otherwise finite and > 0                         */
 } kmc_config;
+
+/* Time step rules.
+ *   KMC_DT_FIXED     every step of box b lasts boxes[b].dt.
+ *   KMC_DT_ADAPTIVE  the adaptive step of Section 1 (dt = dx / v_max, so no
+ *                    particle leaves its neighbourhood within one step),
+ *                    evaluated per box at the start of every step from the
+ *                    current velocities:
+ *                      dx  = min over k of (hi[k] - lo[k]) / ncell[k]
+ *                      v2  = max over the box's particles of
+ *                            fma(vz, vz, fma(vy, vy, vx * vx))
+ *                      dt  = v2 > 0 ? min(boxes[b].dt, (C * dx) / sqrt(v2))
+ *                                   : boxes[b].dt
+ *                    with IEEE-754 binary64 operations in that order (the
+ *                    result is independent of how the maximum is reduced).
+ *                    Section 3 synchronises this step over MPI domains; the
+ *                    boxes of one context are independent and keep their own. */
 
 /* Phases timed in profile mode (indices into kmc_stats.ms). */
 enum {
     KMC_PHASE_BIN = 0,      /* cell index + per-cell count (runs fused into the
                                previous step's resolve; 0 ms in practice)           */
     KMC_PHASE_SCAN = 1,     /* exclusive prefix sum of the counts                   */
-    KMC_PHASE_SCATTER = 2,  /* cell-sorted copy of the state                        */
+    KMC_PHASE_SCATTER = 2,  /* cell-sorted copy of the state, the step's dt, and the
+                               FP32 screen's per-box bounds                         */
     KMC_PHASE_SEARCH = 3,   /* DCA pair search kernel (FP64, or the FP32 screen)    */
     KMC_PHASE_FINISH = 4,   /* closest partner from the recorded candidates         */
     KMC_PHASE_RECHECK = 5,  /* full FP64 re-search of undecided particles           */
@@ -193,8 +224,61 @@ int kmc_read_history(kmc_ctx* ctx, uint64_t* h_npairs, uint64_t* h_digest,
  * before the first step. */
 int kmc_count_pair_tests(kmc_ctx* ctx, uint64_t* h_pair_tests, void* stream);
 
+/* Time step of the last step and simulated time since kmc_init (the sum of
+ * the steps' dt) of each box, into host arrays of `capacity` >= nboxes
+ * doubles (either may be NULL).  Synchronises `stream`. */
+int kmc_read_time(kmc_ctx* ctx, double* h_dt, double* h_time, uint32_t capacity, void* stream);
+
 /* Counters and (profile mode) per-phase times.  Synchronises `stream`. */
 int kmc_get_stats(kmc_ctx* ctx, kmc_stats* out, void* stream);
+
+/* Launch tuning.  kmc_autotune times short runs of candidate
+ * configurations on the caller's input and returns the fastest.
+ *   KMC_TUNE_LAUNCH  search organisation (kmc_search_mode) and threads per
+ *                    block of the streaming kernels; the results of the step
+ *                    do not depend on these;
+ *   KMC_TUNE_CELLS   also the cell edge: every box gets ncell[k] =
+ *                    floor((hi[k] - lo[k]) / (kappa * sqrt(D2))) cells
+ *                    (kappa in {1, 1.25, 1.5, 2}; at least 3 on periodic
+ *                    axes, candidates that violate it are skipped) and
+ *                    inv_h[k] = ncell[k] / (hi[k] - lo[k]).  The cell grid is
+ *                    part of the partner criteria (Section 1: partners are
+ *                    searched in the neighbouring bins), so this changes the
+ *                    results: the caller must use the returned boxes
+ *                    everywhere (including any reference it compares with). */
+enum { KMC_TUNE_LAUNCH = 1, KMC_TUNE_CELLS = 2 };
+
+#define KMC_TUNE_MAX 32
+typedef struct kmc_tuning {
+    uint32_t ntried;                 /* candidates timed                           */
+    uint32_t best;                   /* index of the chosen one                    */
+    double ms_per_step[KMC_TUNE_MAX];/* per candidate (NaN: skipped)               */
+    int32_t search_mode[KMC_TUNE_MAX];
+    int32_t block_size[KMC_TUNE_MAX];
+    double kappa[KMC_TUNE_MAX];      /* cell-edge factor (0: the given grid)       */
+} kmc_tuning;
+
+/* Time every candidate over `steps` steps (after one untimed step) from the
+ * same input, choose the fastest, and write the chosen boxes and
+ * configuration to out_boxes (nboxes entries; equal to `boxes` unless
+ * KMC_TUNE_CELLS) and *out_cfg (cfg with search_mode and block_size set; the
+ * other fields are copied).
+ *   d_state, d_workspace  as for kmc_init; the workspace must hold the
+ *                    largest candidate (kmc_workspace_bytes of the boxes
+ *                    with kappa = 1 and block_size 64 suffices); candidates
+ *                    that do not fit are skipped;
+ *   flags            KMC_TUNE_LAUNCH and/or KMC_TUNE_CELLS (0 = LAUNCH).
+ * d_state is only read.  Synchronises `stream`.  Errors as kmc_init, and
+ * KMC_ENOMEM when no candidate fits. */
+int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,
+                 void* d_workspace, size_t workspace_bytes, uint32_t flags, uint32_t steps, void* stream,
+                 kmc_box* out_boxes, kmc_config* out_cfg, kmc_tuning* out);
+
+/* Cell grid of a box for a cell-edge factor kappa, as KMC_TUNE_CELLS sets
+ * it (host helper, no device work): fills out->ncell and out->inv_h from
+ * box (other fields copied).  KMC_EINVAL if kappa < 1 or a periodic axis
+ * would get fewer than 3 cells. */
+int kmc_box_with_kappa(const kmc_box* box, double kappa, kmc_box* out);
 
 /* Release the host context, its private stream and graph.  The workspace
  * may be freed by the caller afterwards.  NULL is ignored. */

@@ -7,6 +7,7 @@ imports this module.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 
 import numpy as np
@@ -69,11 +70,13 @@ def lib():
         L.orc_pair_hash.restype = C.c_uint64
         L.orc_step.argtypes = [bp, dp, u32p, C.c_uint64, i32p, u64p, u64p, C.c_int, u64p]
         L.orc_count_accepted.argtypes = [bp, dp, u32p, C.c_int, u64p, u64p]
+        L.orc_adaptive_dt.argtypes = [bp, dp, C.c_double, dp]
         L.orc_step_sampled.argtypes = [bp, dp, u32p, C.c_uint64, C.POINTER(C.c_int64), C.c_int64, i32p,
                                        dp, C.c_int]
         L.orc_max_threads.argtypes = []
         for f in ("orc_cell_coords", "orc_pair", "orc_find_partners", "orc_find_partners_bruteforce",
-                  "orc_step", "orc_count_accepted", "orc_step_sampled", "orc_max_threads"):
+                  "orc_step", "orc_count_accepted", "orc_step_sampled", "orc_adaptive_dt",
+                  "orc_max_threads"):
             getattr(L, f).restype = C.c_int
         _LIB = L
     return _LIB
@@ -184,6 +187,18 @@ def pair_hash(a, b):
     return int(lib().orc_pair_hash(int(a), int(b)))
 
 
+def adaptive_dt(box, state, factor=1.0):
+    """The adaptive time step of one box for the given state."""
+    s = _soa(state)
+    ob = make_box(box)
+    ob.n = s.shape[1]
+    out = C.c_double(0.0)
+    rc = lib().orc_adaptive_dt(C.byref(ob), _ptr(s, C.c_double), float(factor), C.byref(out))
+    if rc != 0:
+        raise ValueError(f"orc_adaptive_dt failed ({rc})")
+    return float(out.value)
+
+
 def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0):
     """The oracle step of one box evaluated at the particles `sel` only
     (indices into the box); `state` is not modified.  Returns (partner
@@ -242,6 +257,8 @@ class Run:
         self.nthreads = nthreads
         self.partner_by_id = None
         self.pair_tests = 0
+        self.time = [0.0] * len(workload.boxes)
+        self.dt_last = [float(b.dt) for b in workload.boxes]
 
     def step(self):
         """Advance every box by one step; returns (npairs, digest) summed
@@ -249,6 +266,10 @@ class Run:
         tot_pairs, tot_dig, tests = 0, 0, 0
         pb = np.full(self.off[-1], -1, dtype=np.int64)
         for b, box in enumerate(self.w.boxes):
+            if getattr(self.w, "dt_rule", 0) == 1:
+                box = dataclasses.replace(box, dt=adaptive_dt(box, self.state[b], self.w.dt_factor))
+            self.dt_last[b] = float(box.dt)
+            self.time[b] += float(box.dt)
             p, npairs, dig, t = step_box(box, self.state[b], self.ids[b], self.step_index,
                                          seed=self.w.seed, kinematics=self.w.kinematics,
                                          nthreads=self.nthreads)

@@ -434,6 +434,35 @@ static void apply_bc(const orc_box* b, double x[3], double v[3])
 }
 
 /* ------------------------------------------------------------------------ */
+/* Adaptive time step (Section 1: the step is the bin width over the largest */
+/* particle speed)                                                           */
+/* ------------------------------------------------------------------------ */
+
+int orc_adaptive_dt(const orc_box* b, const double* s, double factor, double* dt)
+{
+    if (!box_ok(b) || !dt || (b->n > 0 && !s) || !(factor > 0.0)) return -1;
+    int64_t n = b->n;
+    double dx = (b->hi[0] - b->lo[0]) / b->ncell[0];
+    for (int k = 1; k < 3; ++k) {
+        double w = (b->hi[k] - b->lo[k]) / b->ncell[k];
+        if (w < dx) dx = w;
+    }
+    double v2max = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double vx = s[3 * n + i], vy = s[4 * n + i], vz = s[5 * n + i];
+        double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+        if (v2 > v2max) v2max = v2;
+    }
+    double step = b->dt;
+    if (v2max > 0.0) {
+        double a = (factor * dx) / sqrt(v2max);
+        if (a < step) step = a;
+    }
+    *dt = step;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* One step (Section 1: search, mutual collisions, update, boundaries)       */
 /* ------------------------------------------------------------------------ */
 

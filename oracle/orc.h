@@ -107,6 +107,13 @@ int orc_step_sampled(const orc_box* b, const double* s, const uint32_t* ids, uin
                      const int64_t* sel, int64_t nsel, int32_t* partner_out,
                      double* state_out, int nthreads);
 
+/* Adaptive time step of Section 1 (dt = dx / v_max: no particle can leave
+ * its neighbourhood within one step), scaled by `factor` and capped by
+ * b->dt: with dx the smallest bin width and v_max the largest particle
+ * speed in s, *dt = min(b->dt, factor * dx / v_max), or b->dt when every
+ * particle is at rest. */
+int orc_adaptive_dt(const orc_box* b, const double* s, double factor, double* dt);
+
 /* Ordered pairs (i, j != i) examined and ordered pairs accepted by the
  * partner criteria in the current state, without choosing partners; used by
  * the collision-rate check. */

@@ -70,6 +70,9 @@ int check_cfg(const kmc_config& c)
     if (c.profile != 0 && c.profile != 1) return KMC_EINVAL;
     if (!std::isfinite(c.guard_scale) || (c.guard_scale != 0.0 && c.guard_scale != -1.0 && c.guard_scale < 1.0))
         return KMC_EINVAL;
+    if (c.dt_rule != KMC_DT_FIXED && c.dt_rule != KMC_DT_ADAPTIVE) return KMC_EINVAL;
+    if (c.search_mode != KMC_SEARCH_HALF && c.search_mode != KMC_SEARCH_FULL) return KMC_EINVAL;
+    if (c.dt_factor != 0.0 && !finite_pos(c.dt_factor)) return KMC_EINVAL;
     for (int r : c.reserved)
         if (r != 0) return KMC_EINVAL;
     return KMC_OK;
@@ -116,7 +119,6 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     const size_t N = t.N, C = t.C;
     const uint32_t H = history_len(cfg);
     const uint32_t nblk = (uint32_t)((C + kScanTile - 1) / kScanTile);
-    const bool f32 = cfg.precision == KMC_FP32_SCREEN;
     const uint32_t cap = cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N;
     p.ctl = (Ctl*)take(sizeof(Ctl));
     p.boxes = (BoxDev*)take(sizeof(BoxDev) * nboxes);
@@ -128,6 +130,8 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     const uint32_t nblk_part = (uint32_t)((N + blk - 1) / blk);
     p.vmax_part = (float*)take(sizeof(float) * (nblk_part ? nblk_part : 1));
     p.box_vmax = (unsigned int*)take(sizeof(unsigned int) * nboxes);
+    p.v2_part = (unsigned long long*)take(sizeof(unsigned long long) * (nblk_part ? nblk_part : 1));
+    p.box_v2 = (unsigned long long*)take(sizeof(unsigned long long) * nboxes);
     p.box_sb = (ScreenBounds*)take(sizeof(ScreenBounds) * nboxes);
     p.idA = (uint32_t*)take(4 * N);
     p.idB = (uint32_t*)take(4 * N);
@@ -157,6 +161,9 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.block = cfg.block_size ? cfg.block_size : 256;
     p.nblk_part = nblk_part;
     p.guard = cfg.guard_scale > 0.0 ? (float)cfg.guard_scale : (cfg.guard_scale < 0.0 ? 0.0f : 4.0f);
+    p.dt_rule = cfg.dt_rule;
+    p.search_mode = cfg.search_mode;
+    p.dt_factor = cfg.dt_factor != 0.0 ? cfg.dt_factor : 1.0;
     return off;
 }
 
@@ -187,6 +194,13 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
     }
     d.D2 = b.D2;
     d.dt = b.dt;
+    d.dt_cap = b.dt;
+    d.dx = d.L[0] / (double)b.ncell[0];
+    for (int k = 1; k < 3; ++k) {
+        const double e = d.L[k] / (double)b.ncell[k];
+        if (e < d.dx) d.dx = e;
+    }
+    d.time = 0.0;
     d.sphere = b.geometry == KMC_GEOM_SPHERE ? 1 : 0;
     d.R = b.sphere_r;
     d.R2 = b.sphere_r * b.sphere_r;
@@ -382,6 +396,23 @@ int kmc_count_pair_tests(kmc_ctx* c, uint64_t* h_pair_tests, void* stream)
     return KMC_OK;
 }
 
+int kmc_read_time(kmc_ctx* c, double* h_dt, double* h_time, uint32_t capacity, void* stream)
+{
+    if (!c) return KMC_EINVAL;
+    const uint32_t nb = c->plan.nboxes;
+    if ((h_dt || h_time) && capacity < nb) return KMC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<BoxDev> bd(nb);
+    hipError_t e = hipMemcpyAsync(bd.data(), c->plan.boxes, sizeof(BoxDev) * nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return KMC_EDEVICE;
+    for (uint32_t b = 0; b < nb; ++b) {
+        if (h_dt) h_dt[b] = bd[b].dt;
+        if (h_time) h_time[b] = bd[b].time;
+    }
+    return KMC_OK;
+}
+
 int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
 {
     if (!c || !out) return KMC_EINVAL;
@@ -409,6 +440,110 @@ int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
     for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
     out->search_kernel_ms = c->search_kernel_ms;
     out->timed_steps = c->timed_steps;
+    return KMC_OK;
+}
+
+int kmc_box_with_kappa(const kmc_box* box, double kappa, kmc_box* out)
+{
+    if (!box || !out || !std::isfinite(kappa) || !(kappa >= 1.0)) return KMC_EINVAL;
+    if (check_box(*box) != KMC_OK) return KMC_EINVAL;
+    kmc_box b = *box;
+    const double D = std::sqrt(box->D2);
+    for (int k = 0; k < 3; ++k) {
+        const double L = box->hi[k] - box->lo[k];
+        double m = std::floor(L / (kappa * D));
+        if (m < 1.0) m = 1.0;
+        if (m > 2147483647.0) return KMC_EOVERFLOW;
+        if (box->bc[k] == KMC_BC_PERIODIC && m < 3.0) return KMC_EINVAL;
+        b.ncell[k] = (int32_t)m;
+        b.inv_h[k] = m / L;
+    }
+    if (check_box(b) != KMC_OK) return KMC_EINVAL;
+    *out = b;
+    return KMC_OK;
+}
+
+int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,
+                 void* d_workspace, size_t workspace_bytes, uint32_t flags, uint32_t steps, void* stream,
+                 kmc_box* out_boxes, kmc_config* out_cfg, kmc_tuning* out)
+{
+    if (!out_boxes || !out_cfg || !out || !d_workspace) return KMC_EINVAL;
+    Totals t;
+    int rc = validate(boxes, nboxes, cfg, t);
+    if (rc != KMC_OK) return rc;
+    if (t.N > 0 && !d_state) return KMC_EINVAL;
+    if (flags == 0) flags = KMC_TUNE_LAUNCH;
+    if (flags & ~(uint32_t)(KMC_TUNE_LAUNCH | KMC_TUNE_CELLS)) return KMC_EINVAL;
+    if (steps == 0) steps = 3;
+    if (steps > 1000) return KMC_EINVAL;
+
+    std::vector<double> kappas{0.0};
+    if (flags & KMC_TUNE_CELLS) kappas = {1.0, 1.25, 1.5, 2.0};
+    std::vector<int32_t> modes{cfg->search_mode}, blocks{cfg->block_size ? cfg->block_size : 256};
+    if (flags & KMC_TUNE_LAUNCH) {
+        modes = {KMC_SEARCH_HALF, KMC_SEARCH_FULL};
+        blocks = {128, 256, 512};
+    }
+    std::memset(out, 0, sizeof(*out));
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return KMC_EDEVICE;
+    }
+    std::vector<kmc_box> bx(boxes, boxes + nboxes), best_boxes;
+    kmc_config best_cfg{};
+    double best_ms = INFINITY;
+    int status = KMC_OK;
+    uint32_t k = 0;
+    for (double kappa : kappas) {
+        bool ok = true;
+        for (uint32_t b = 0; b < nboxes && ok; ++b)
+            ok = kappa == 0.0 ? (bx[b] = boxes[b], true) : kmc_box_with_kappa(&boxes[b], kappa, &bx[b]) == KMC_OK;
+        for (int32_t mode : modes)
+            for (int32_t blk : blocks) {
+                if (k >= KMC_TUNE_MAX) break;
+                out->search_mode[k] = mode;
+                out->block_size[k] = blk;
+                out->kappa[k] = kappa;
+                out->ms_per_step[k] = NAN;
+                kmc_config c = *cfg;
+                c.search_mode = mode;
+                c.block_size = blk;
+                c.use_graph = 0;
+                c.profile = 0;
+                size_t need = 0;
+                kmc_ctx* ctx = nullptr;
+                if (ok && kmc_workspace_bytes(bx.data(), nboxes, &c, &need) == KMC_OK && need <= workspace_bytes &&
+                    kmc_init(bx.data(), nboxes, &c, d_state, d_workspace, workspace_bytes, stream, &ctx) == KMC_OK) {
+                    float ms = 0.f;
+                    hipError_t e = kmc_step(ctx, 1, stream) == KMC_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
+                    if (e == hipSuccess) e = kmc_step(ctx, steps, stream) == KMC_OK ? hipEventRecord(e1, s) : hipErrorUnknown;
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    kmc_destroy(ctx);
+                    if (e != hipSuccess) { status = KMC_EDEVICE; break; }
+                    out->ms_per_step[k] = ms / steps;
+                    if (ms / steps < best_ms) {
+                        best_ms = ms / steps;
+                        out->best = k;
+                        best_boxes = bx;
+                        best_cfg = c;
+                    }
+                }
+                ++k;
+            }
+        if (status != KMC_OK) break;
+    }
+    out->ntried = k;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (status != KMC_OK) return status;
+    if (best_boxes.empty()) return KMC_ENOMEM;
+    std::copy(best_boxes.begin(), best_boxes.end(), out_boxes);
+    *out_cfg = *cfg;
+    out_cfg->search_mode = best_cfg.search_mode;
+    out_cfg->block_size = best_cfg.block_size;
     return KMC_OK;
 }
 

@@ -225,6 +225,7 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
         p.hist_dig[k] = 0;
         p.cand_acc[k] = 0;
     }
+    for (uint32_t b = t; b < p.nboxes; b += blockDim.x) p.box_v2[b] = 0ull;
 }
 
 __global__ void k_read_partners(Plan p, int32_t* __restrict__ out)
@@ -397,31 +398,107 @@ __global__ void k_scatter(Plan p)
     const bool valid = i < p.N;
     const size_t N = p.N;
     float vm = 0.f;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
     if (valid) {
         const uint32_t d = p.start[p.cell[i]] + p.slot[i];
         P64 r;
         r.x = p.A[i];
         r.y = p.A[N + i];
         r.z = p.A[2 * N + i];
-        r.vx = p.A[3 * N + i];
-        r.vy = p.A[4 * N + i];
-        r.vz = p.A[5 * N + i];
+        r.vx = vx = p.A[3 * N + i];
+        r.vy = vy = p.A[4 * N + i];
+        r.vz = vz = p.A[5 * N + i];
         p.B[d] = r;
         p.idB[d] = p.idA[i];
         if (F32) vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
     }
+    __shared__ float wmax[16];
+    __shared__ unsigned long long wv2[16];
     if (F32) {
         // per-block maximum of |fl32(v_k)|; k_vmax_reduce folds the blocks of each box
-        __shared__ float wmax[16];
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off, 64));
         if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = vm;
+    }
+    if (p.dt_rule == KMC_DT_ADAPTIVE) {
+        // adaptive time step: max |v|^2 per box.  Non-negative doubles order
+        // like their bit patterns, so the maximum is exact in any order.  The
+        // block folds its particles that share the box of its first particle
+        // (k_adapt_dt reads the partial); any others go to their box directly.
+        const uint32_t first = blockIdx.x * blockDim.x;
+        const uint32_t b0 = p.boxidx ? p.boxidx[first] : 0u;
+        unsigned long long q = 0ull;
+        if (valid) {
+            const double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
+            const unsigned long long bits = (unsigned long long)__double_as_longlong(v2);
+            const uint32_t bi = p.boxidx ? p.boxidx[i] : 0u;
+            if (bi == b0) q = bits;
+            else atomicMax(&p.box_v2[bi], bits);
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(q, off, 64);
+            q = o > q ? o : q;
+        }
+        if ((threadIdx.x & 63) == 0) wv2[threadIdx.x >> 6] = q;
+    }
+    if (F32 || p.dt_rule == KMC_DT_ADAPTIVE) {
         __syncthreads();
         if (threadIdx.x == 0) {
-            float m = 0.f;
-            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, wmax[w]);
-            p.vmax_part[blockIdx.x] = m;
+            const int nw = (int)(blockDim.x >> 6);
+            if (F32) {
+                float m = 0.f;
+                for (int w = 0; w < nw; ++w) m = fmaxf(m, wmax[w]);
+                p.vmax_part[blockIdx.x] = m;
+            }
+            if (p.dt_rule == KMC_DT_ADAPTIVE) {
+                unsigned long long m = 0ull;
+                for (int w = 0; w < nw; ++w) m = wv2[w] > m ? wv2[w] : m;
+                p.v2_part[blockIdx.x] = m;
+            }
         }
+    }
+}
+
+// This step's time step of every box (one block per box), from the maxima
+// k_scatter gathered: dt = min(cap, (C dx) / sqrt(max |v|^2)) under the
+// adaptive rule, the configured dt otherwise; also the simulated time.
+__global__ __launch_bounds__(256) void k_adapt_dt(Plan p)
+{
+    __shared__ unsigned long long red[256];
+    const uint32_t b = blockIdx.x;
+    BoxDev& B = p.boxes[b];
+    unsigned long long m = 0ull;
+    if (p.dt_rule == KMC_DT_ADAPTIVE && B.n > 0) {
+        // the scatter blocks whose first particle lies in this box
+        const uint32_t blk = (uint32_t)p.block;
+        const uint32_t k0 = (B.poff + blk - 1) / blk, k1 = (B.poff + B.n - 1) / blk;
+        for (uint32_t k = k0 + threadIdx.x; k <= k1; k += blockDim.x) {
+            const unsigned long long v = p.v2_part[k];
+            m = v > m ? v : m;
+        }
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (uint32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] > red[threadIdx.x] ? red[threadIdx.x + w] : red[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (p.dt_rule == KMC_DT_ADAPTIVE) {
+            const unsigned long long o = p.box_v2[b];
+            const unsigned long long mm = o > red[0] ? o : red[0];
+            p.box_v2[b] = 0ull;
+            const double v2 = __longlong_as_double((long long)mm);
+            double dt = B.dt_cap;
+            if (v2 > 0.0) {
+                const double a = (p.dt_factor * B.dx) / sqrt(v2);
+                if (a < dt) dt = a;
+            }
+            B.dt = dt;
+            B.dt_32 = (float)dt;
+        }
+        B.time = B.time + B.dt;
     }
 }
 
@@ -587,8 +664,27 @@ struct Found {
 struct NoGroup {
 };
 
+// Running (key, id) minimum of one lane in the full-neighbourhood search.
+struct Best {
+    double key;
+    uint32_t id;
+    int32_t j;
+    uint32_t accepted;   // acceptable pairs seen (statistics)
+    uint32_t screened;   // FP32 screen: pairs decided in FP64
+    __device__ __forceinline__ void offer(double k, uint32_t idj, uint32_t jj)
+    {
+        accepted += 1u;
+        if (k < key || (k == key && idj < id)) {
+            key = k;
+            id = idj;
+            j = (int32_t)jj;
+        }
+    }
+};
+
 struct PolF64 {
     static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
+    static constexpr bool kScreen = false;
     struct Lds {
         P64 rec[W];
     };
@@ -619,6 +715,23 @@ struct PolF64 {
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
             if (accept(pq, D2, dt)) f.add(p, i, j);
+        }
+    }
+    // full neighbourhood: running (key, id) minimum over the acceptable pairs
+    // (the particle itself has g2 = 0 and is never accepted)
+    template <bool SH>
+    __device__ static void scan_best(const Plan&, const Lds& l, const uint32_t* lid, uint32_t c0, uint32_t j0,
+                                     uint32_t j1, uint32_t, const Own& o, const BoxDev& B, const Group&, int wx,
+                                     int wy, int wz, Best& best)
+    {
+        const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
+        const double D2 = B.D2, dt = B.dt;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const P64 q = l.rec[j - c0];
+            double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
+            if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
+            if (accept(pq, D2, dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
         }
     }
 };
@@ -718,6 +831,7 @@ struct alignas(16) Rec32 {
 
 struct PolF32 {
     static constexpr int W = 160;         // staged records per chunk (5 KiB)
+    static constexpr bool kScreen = true;
     struct Lds {
         Rec32 r[W];
     };
@@ -783,6 +897,40 @@ struct PolF32 {
                 // certainly acceptable in FP64: recorded with the flag bit
                 const bool sure = (b < -Tb) & (m2 < -Tt) & (m3 < -Tc) & (g2 > fmaf(g.t.tg1, g2, g.t.tg0));
                 f.add(p, i, j | (sure ? kSureBit : 0u));
+            }
+        }
+    }
+    // full neighbourhood: every pair the screen cannot reject is decided in
+    // FP64 from the sorted records, with the image shift of its cell
+    template <bool SH>
+    __device__ static void scan_best(const Plan& p, const Lds& l, const uint32_t* lid, uint32_t c0, uint32_t j0,
+                                     uint32_t j1, uint32_t i, const Own& o, const BoxDev& B, const Group& g,
+                                     int wx, int wy, int wz, Best& best)
+    {
+        const float D2 = B.D2_32, dt = B.dt_32;
+        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, tt1 = g.t.tt1, tc0 = g.t.tc0, tc1 = g.t.tc1;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const float4 qa = l.r[j - c0].a;
+            const float2 qb = l.r[j - c0].b;
+            const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
+            const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
+            const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
+            const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+            const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const float m2 = fmaf(-dt, g2, -b);
+            const float m3 = fmaf(rr - D2, g2, -(b * b));
+            const float Tb = fmaf(tb1, g2, tb0), Tt = fmaf(tt1, g2, tt0), Tc = fmaf(tc1, g2, tc0);
+            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc) & (j != i)) {
+                const P64 me = p.B[i], q = p.B[j];
+                double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
+                if (SH) {
+                    rx6 = rx6 + (double)wx * B.L[0];
+                    ry6 = ry6 + (double)wy * B.L[1];
+                    rz6 = rz6 + (double)wz * B.L[2];
+                }
+                const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+                best.screened += 1u;
+                if (accept(pq, B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
             }
         }
     }
@@ -885,6 +1033,103 @@ void k_search_half(Plan p)
         }
     }
     if (valid) found.flush(p, i);
+}
+
+// Full-neighbourhood variant of the search (KMC_SEARCH_FULL): every
+// particle scans its own and all 26 neighbouring cells and keeps the running
+// (key, id) minimum in registers, writing its partner directly.  It tests
+// every pair twice but records nothing, so it suits dense cells with many
+// acceptable partners per particle, where the candidate lists of the
+// half-neighbourhood search overflow.  Rows and staging as in k_search_half.
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KMC_SEARCH_WAVES_PER_EU)))
+void k_search_full(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    __shared__ uint32_t lid[Pol::W];
+    const int lane = threadIdx.x;
+    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * 64u + (uint32_t)lane;
+    const bool valid = i < p.N;
+    uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
+    int cx = 0, cy = 0, cz = 0;
+    typename Pol::Own own;
+    if (valid) {
+        bidx = p.boxidx ? p.boxidx[i] : 0u;
+        const BoxDev& B = p.boxes[bidx];
+        double x, y, z;
+        Pol::load_own(p, i, own, x, y, z);
+        cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
+        cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
+        cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
+        rowkey = B.coff + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+    }
+    Best best;
+    best.key = __builtin_inf();
+    best.id = 0xFFFFFFFFu;
+    best.j = -1;
+    best.accepted = 0u;
+    best.screened = 0u;
+    uint64_t remaining = __ballot(valid);
+    while (remaining) {
+        const int lead = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
+        const uint64_t grp = __ballot(valid && rowkey == key) & remaining;
+        remaining &= ~grp;
+        const bool in = (grp >> lane) & 1ull;
+        const int last = 63 - __clzll((long long)grp);
+        const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
+        const BoxDev& B = p.boxes[gb];
+        const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
+        const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
+        const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
+        typename Pol::Group gctx;
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb);
+        auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
+            const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];
+            const bool sh = (wx | wy | wz) != 0;
+            for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
+                const uint32_t n = min((uint32_t)Pol::W, ge - c0);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) {
+                    Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz);
+                    lid[t] = p.idB[c0 + t];
+                }
+                __syncthreads();
+                const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
+                if (sh) Pol::template scan_best<true>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, best);
+                else Pol::template scan_best<false>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, best);
+                __syncthreads();
+            }
+        };
+        auto wrap_cell = [&](uint32_t row, int cell, bool use, int wx, int wy, int wz) {
+            part(row, cell, cell, use ? 0u : 1u, use ? 0xFFFFFFFFu : 0u, wx, wy, wz);
+        };
+        for (int r = 0; r < 9; ++r) {
+            const int dy = r % 3 - 1, dz = r / 3 - 1;
+            int nz = gcz + dz, wz = 0;
+            if (nz < 0) { if (!B.periodic[2]) continue; nz += NZ; wz = -1; }
+            else if (nz >= NZ) { if (!B.periodic[2]) continue; nz -= NZ; wz = 1; }
+            int ny = gcy + dy, wy = 0;
+            if (ny < 0) { if (!B.periodic[1]) continue; ny += NY; wy = -1; }
+            else if (ny >= NY) { if (!B.periodic[1]) continue; ny -= NY; wy = 1; }
+            const uint32_t row = B.coff + (uint32_t)NX * ((uint32_t)ny + (uint32_t)NY * (uint32_t)nz);
+            uint32_t ls = 0, le = 0;
+            if (in) {
+                ls = p.start[row + (cx - 1 < 0 ? 0 : cx - 1)];
+                le = p.start[row + (cx + 1 >= NX ? NX - 1 : cx + 1) + 1];
+            }
+            part(row, cxf - 1 < 0 ? 0 : cxf - 1, cxl + 1 >= NX ? NX - 1 : cxl + 1, ls, le, 0, wy, wz);
+            if (B.periodic[0]) {
+                if (cxf - 1 < 0) wrap_cell(row, NX - 1, in && cx == 0, -1, wy, wz);
+                if (cxl + 1 >= NX) wrap_cell(row, 0, in && cx == NX - 1, 1, wy, wz);
+            }
+        }
+    }
+    if (valid) p.partner[i] = best.j;
+    // statistics: pairs accepted (FP64) or decided in FP64 (FP32 screen)
+    uint64_t c = Pol::kScreen ? best.screened : best.accepted;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c);
 }
 
 // Pairs beyond a search lane's register slots, into both candidate lists.
@@ -1179,6 +1424,7 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         if (p.precision == KMC_FP32_SCREEN) k_scatter<true><<<gN, b, 0, s>>>(p);
         else k_scatter<false><<<gN, b, 0, s>>>(p);
     }
+    k_adapt_dt<<<p.nboxes, 256, 0, s>>>(p);
     mark(KMC_PHASE_SEARCH);
     const uint32_t gW = blocks_for(p.N, 64);
     if (p.precision == KMC_FP32_SCREEN) {
@@ -1186,18 +1432,24 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         k_screen_bounds<<<blocks_for(p.nboxes, 64), 64, 0, s>>>(p);
     }
     if (ev) (void)hipEventRecord(ev[KMC_PHASE_COUNT + 1], s);   // search kernel alone
+    const bool full = p.search_mode == KMC_SEARCH_FULL;
     if (p.N > 0) {
-        if (p.precision == KMC_FP32_SCREEN) k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
-        else k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
+        if (full) {
+            if (p.precision == KMC_FP32_SCREEN) k_search_full<PolF32><<<gW, 64, 0, s>>>(p);
+            else k_search_full<PolF64><<<gW, 64, 0, s>>>(p);
+        } else {
+            if (p.precision == KMC_FP32_SCREEN) k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
+            else k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
+        }
     }
     mark(KMC_PHASE_FINISH);
-    if (p.N > 0) k_distribute_overflow<<<256, 256, 0, s>>>(p);
-    if (p.N > 0) {
+    if (p.N > 0 && !full) {
+        k_distribute_overflow<<<256, 256, 0, s>>>(p);
         if (p.precision == KMC_FP32_SCREEN) k_finish<true><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
         else k_finish<false><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RECHECK);
-    if (p.N > 0) {
+    if (p.N > 0 && !full) {
         k_recheck64<<<128, 256, 0, s>>>(p);
         k_fallback64<<<512, 256, 0, s>>>(p);
     }

@@ -37,6 +37,10 @@ struct alignas(16) BoxDev {
     float er[3];         // bound on |r_hat_k - r_k| for any neighbour pair
     float pad_;
     double rmax[3];      // bound on |r_k| for any neighbour pair (2 h_k)
+    // time step: dt above is this step's; dt_cap is the box's configured step
+    // (the adaptive rule's upper bound), dx the smallest cell edge
+    // (hi_k - lo_k) / nc_k, time the simulated time since initialisation
+    double dx, dt_cap, time;
 };
 
 // Cell-sorted FP64 particle record (48 bytes, 16-byte aligned).
@@ -93,6 +97,9 @@ struct Plan {
     uint32_t* recheck;             // sorted indices to re-search in full FP64
     uint2* ovf;                    // pairs a search lane found beyond its register slots
     unsigned long long* cand_acc;  // kHistLanes accumulators of recorded candidates
+    unsigned long long* v2_part;   // adaptive dt: per scatter block, max |v|^2 (FP64 bits) of
+                                   // its particles in the box of its first particle
+    unsigned long long* box_v2;    // adaptive dt: per box, max |v|^2 of the other particles
     uint32_t N, C, nboxes, H;
     uint32_t nblk_scan;
     uint32_t recheck_cap;
@@ -101,6 +108,9 @@ struct Plan {
     int32_t precision, kinematics, block;
     uint32_t nblk_part;            // scatter blocks (entries of vmax_part)
     float guard;                   // FP32 screen: scale of the rounding-error bounds (>= 1)
+    int32_t dt_rule;               // kmc_dt_rule
+    int32_t search_mode;           // kmc_search_mode
+    double dt_factor;              // adaptive dt: C in dt = min(cap, C dx / v_max)
 };
 
 // Kernel launchers (kmc_device.hip).  `ev`, when not null, points to

@@ -69,6 +69,8 @@ class Workload:
     steps: int
     seed: int = 1
     kinematics: int = 0          # 0: scatter at t*, 1: velocity-only
+    dt_rule: int = 0             # 0: fixed dt per box, 1: adaptive (box dt is the cap)
+    dt_factor: float = 1.0       # adaptive rule: factor C in dt = C dx / v_max
     info: dict = field(default_factory=dict)
 
     @property

@@ -20,6 +20,8 @@ KMC_FP64, KMC_FP32_SCREEN = 0, 1
 KMC_GEOM_BOX, KMC_GEOM_SPHERE = 0, 1
 KMC_BC_REFLECT, KMC_BC_PERIODIC = 0, 1
 KMC_KIN_AT_TSTAR, KMC_KIN_VEL_ONLY = 0, 1
+KMC_DT_FIXED, KMC_DT_ADAPTIVE = 0, 1
+KMC_SEARCH_HALF, KMC_SEARCH_FULL = 0, 1
 PHASES = ("bin", "scan", "scatter", "search", "finish", "recheck", "resolve")
 
 _lib = None
@@ -51,8 +53,11 @@ class KmcConfig(C.Structure):
         ("use_graph", C.c_int32),
         ("block_size", C.c_int32),
         ("profile", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("dt_rule", C.c_int32),
+        ("search_mode", C.c_int32),
+        ("reserved", C.c_int32 * 3),
         ("guard_scale", C.c_double),
+        ("dt_factor", C.c_double),
     ]
 
 
@@ -71,8 +76,23 @@ class KmcStats(C.Structure):
 
 
 EXPORTS = ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "kmc_read_state",
-           "kmc_read_history", "kmc_count_pair_tests", "kmc_get_stats", "kmc_destroy",
-           "kmc_strerror", "kmc_abi_version")
+           "kmc_read_history", "kmc_read_time", "kmc_count_pair_tests", "kmc_get_stats", "kmc_destroy",
+           "kmc_strerror", "kmc_abi_version", "kmc_autotune", "kmc_box_with_kappa")
+
+
+KMC_TUNE_LAUNCH, KMC_TUNE_CELLS = 1, 2
+KMC_TUNE_MAX = 32
+
+
+class KmcTuning(C.Structure):
+    _fields_ = [
+        ("ntried", C.c_uint32),
+        ("best", C.c_uint32),
+        ("ms_per_step", C.c_double * KMC_TUNE_MAX),
+        ("search_mode", C.c_int32 * KMC_TUNE_MAX),
+        ("block_size", C.c_int32 * KMC_TUNE_MAX),
+        ("kappa", C.c_double * KMC_TUNE_MAX),
+    ]
 
 
 class KmcError(RuntimeError):
@@ -97,15 +117,20 @@ def load(path=LIB_PATH):
     L.kmc_read_state.argtypes = [vp, vp, vp]
     L.kmc_read_history.argtypes = [vp, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64), C.c_uint32,
                                    C.POINTER(C.c_uint32), vp]
+    L.kmc_read_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_uint32, vp]
     L.kmc_count_pair_tests.argtypes = [vp, C.POINTER(C.c_uint64), vp]
     L.kmc_get_stats.argtypes = [vp, C.POINTER(KmcStats), vp]
+    L.kmc_autotune.argtypes = [bp, C.c_uint32, cp, vp, vp, sz, C.c_uint32, C.c_uint32, vp, bp, cp,
+                               C.POINTER(KmcTuning)]
+    L.kmc_box_with_kappa.argtypes = [bp, C.c_double, bp]
     L.kmc_destroy.argtypes = [vp]
     L.kmc_destroy.restype = None
     L.kmc_strerror.argtypes = [C.c_int]
     L.kmc_strerror.restype = C.c_char_p
     L.kmc_abi_version.argtypes = []
     for f in ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "kmc_read_state",
-              "kmc_read_history", "kmc_count_pair_tests", "kmc_get_stats", "kmc_abi_version"):
+              "kmc_read_history", "kmc_read_time", "kmc_count_pair_tests", "kmc_get_stats", "kmc_abi_version",
+              "kmc_autotune", "kmc_box_with_kappa"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -139,7 +164,8 @@ def make_boxes(boxes):
 
 
 def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR, history=0,
-                recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0):
+                recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0,
+                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF):
     c = KmcConfig()
     c.seed = int(seed) & ((1 << 64) - 1)
     c.step0 = int(step0)
@@ -151,7 +177,54 @@ def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR
     c.block_size = int(block_size)
     c.profile = 1 if profile else 0
     c.guard_scale = float(guard_scale)
+    c.dt_rule = int(dt_rule)
+    c.dt_factor = float(dt_factor)
+    c.search_mode = int(search_mode)
     return c
+
+
+def _box_from_kmc(kb, like):
+    """inputs.Box-like copy of `like` with the grid of the kmc_box kb."""
+    import dataclasses
+    return dataclasses.replace(like, ncell=tuple(int(kb.ncell[k]) for k in range(3)))
+
+
+def box_with_kappa(box, kappa):
+    """The box with the cell grid floor(L / (kappa D)) of KMC_TUNE_CELLS."""
+    src = make_boxes([box])
+    out = KmcBox()
+    _check(load().kmc_box_with_kappa(src, float(kappa), C.byref(out)), "kmc_box_with_kappa")
+    nb = _box_from_kmc(out, box)
+    if tuple(nb.inv_h) != tuple(out.inv_h):
+        raise KmcError("inv_h of the tuned grid differs from ncell / (hi - lo)")
+    return nb
+
+
+def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, **config):
+    """Run kmc_autotune on `state`; returns (boxes, config dict, tuning dict).
+    The boxes differ from the input only with KMC_TUNE_CELLS."""
+    import torch
+    boxes = list(boxes)
+    cfg = make_config(**config)
+    arr = make_boxes(boxes)
+    st = torch.as_tensor(state, dtype=torch.float64).to(device).contiguous()
+    # the largest candidate: the finest grid (kappa = 1) and the smallest blocks
+    probe = [box_with_kappa(b, 1.0) for b in boxes] if flags & KMC_TUNE_CELLS else boxes
+    need = workspace_bytes(probe, make_config(**dict(config, block_size=64)))
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=device)
+    ptr = (ws.data_ptr() + 255) // 256 * 256
+    out_b = (KmcBox * len(boxes))()
+    out_c = KmcConfig()
+    tun = KmcTuning()
+    stream = C.c_void_p(torch.cuda.current_stream(torch.device(device)).cuda_stream)
+    _check(load().kmc_autotune(arr, len(boxes), C.byref(cfg), C.c_void_p(st.data_ptr()), C.c_void_p(ptr),
+                               C.c_size_t(need), int(flags), int(steps), stream, out_b, C.byref(out_c),
+                               C.byref(tun)), "kmc_autotune")
+    new_boxes = [_box_from_kmc(out_b[k], boxes[k]) for k in range(len(boxes))]
+    new_cfg = dict(config, search_mode=int(out_c.search_mode), block_size=int(out_c.block_size))
+    tried = [dict(ms_per_step=tun.ms_per_step[k], search_mode=tun.search_mode[k], block_size=tun.block_size[k],
+                  kappa=tun.kappa[k]) for k in range(tun.ntried)]
+    return new_boxes, new_cfg, dict(best=int(tun.best), tried=tried)
 
 
 def workspace_bytes(boxes, config):
@@ -220,6 +293,16 @@ class Sim:
                                        dg.ctypes.data_as(C.POINTER(C.c_uint64)), cap, C.byref(cnt),
                                        self._stream()), "kmc_read_history")
         return np_[:cnt.value], dg[:cnt.value]
+
+    def time(self):
+        """(dt of the last step, simulated time) per box, float64 numpy arrays."""
+        nb = len(self.boxes)
+        dt = np.zeros(nb, dtype=np.float64)
+        tm = np.zeros(nb, dtype=np.float64)
+        _check(load().kmc_read_time(self._ctx, dt.ctypes.data_as(C.POINTER(C.c_double)),
+                                    tm.ctypes.data_as(C.POINTER(C.c_double)), nb, self._stream()),
+               "kmc_read_time")
+        return dt, tm
 
     def pair_tests(self):
         t = C.c_uint64(0)

@@ -26,13 +26,13 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(kmc.EXPORTS)
-    assert L.kmc_abi_version() == 1
+    assert L.kmc_abi_version() == 2
 
 
 def test_struct_sizes_match_header():
-    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 72 bytes
+    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes
     assert C.sizeof(kmc.KmcBox) == 128
-    assert C.sizeof(kmc.KmcConfig) == 72
+    assert C.sizeof(kmc.KmcConfig) == 80
     assert C.sizeof(kmc.KmcStats) == 128
 
 
@@ -79,6 +79,8 @@ def test_invalid_boxes_rejected(mutate):
 
 @pytest.mark.parametrize("cfg", [
     dict(precision=7), dict(kinematics=3), dict(block_size=100), dict(block_size=2048),
+    dict(dt_rule=2), dict(dt_rule=1, dt_factor=-1.0), dict(dt_rule=1, dt_factor=float("inf")),
+    dict(search_mode=2), dict(search_mode=-1),
 ])
 def test_invalid_configs_rejected(cfg):
     assert _ws([_good()], **cfg)[0] == kmc.KMC_EINVAL
@@ -87,7 +89,7 @@ def test_invalid_configs_rejected(cfg):
 def test_reserved_config_words_must_be_zero():
     arr = kmc.make_boxes([_good()])
     c = kmc.make_config()
-    c.reserved[3] = 1
+    c.reserved[2] = 1
     n = C.c_size_t(0)
     assert kmc.load().kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
 
@@ -107,3 +109,20 @@ def test_null_arguments():
     assert L.kmc_workspace_bytes(kmc.make_boxes([_good()]), 0, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
     assert L.kmc_strerror(-1) == b"invalid argument"
     L.kmc_destroy(None)
+
+
+def test_box_with_kappa_grid():
+    """The cell grid of the autotuner's cell-edge candidates (host helper)."""
+    b = I.Box(n=10, lo=(0, 0, -1), hi=(1, 2, 1), ncell=(10, 20, 20), periodic=(True, True, False),
+              D2=0.09 ** 2, dt=0.01)
+    for kappa, want in [(1.0, (11, 22, 22)), (1.25, (8, 17, 17)), (2.0, (5, 11, 11))]:
+        nb = kmc.box_with_kappa(b, kappa)
+        assert nb.ncell == want
+        assert all(nb.h[k] >= kappa * 0.09 for k in range(3))
+        assert nb.n == b.n and nb.lo == b.lo and nb.D2 == b.D2
+    with pytest.raises(kmc.KmcError):
+        kmc.box_with_kappa(b, 0.5)
+    small = I.Box(n=10, lo=(0, 0, 0), hi=(0.25, 1, 1), ncell=(3, 3, 3), periodic=(True,) * 3, D2=0.08 ** 2, dt=0.1)
+    kmc.box_with_kappa(small, 1.0)              # 3 cells: allowed
+    with pytest.raises(kmc.KmcError):
+        kmc.box_with_kappa(small, 1.25)         # 2 cells on a periodic axis

@@ -40,6 +40,8 @@ def _prec(kmc, name):
 def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
     print(f"\n[parity] {w.name} N={w.n} boxes={len(w.boxes)} steps={steps} {precision} cfg={cfg}", flush=True)
     cfg["precision"] = _prec(kmc, precision)
+    if w.dt_rule:
+        cfg.update(dt_rule=w.dt_rule, dt_factor=w.dt_factor)
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics, **cfg)
     ref = O.Run(w)
     digests = []
@@ -59,6 +61,8 @@ def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
     rel = state_close(st, ref_st, w.boxes, w.offsets)
     assert rel <= 1e-12, f"state differs by {rel:.3e} relative"
     exact = bool(np.array_equal(st, ref_st))
+    dt, tm = sim.time()
+    assert list(dt) == ref.dt_last and list(tm) == ref.time, "time steps differ"
     stats = sim.stats()
     print(f"[parity] ok exact={exact} rechecks={stats['rechecks']} fallbacks={stats['fallbacks']}", flush=True)
     sim.close()
@@ -191,3 +195,64 @@ def test_pair_test_count_matches_oracle(kmc):
     ref.step()
     assert sim.pair_tests() == ref.pair_tests
     sim.close()
+
+
+def _adaptive(w, factor, cap_scale):
+    import dataclasses
+    w.boxes = [dataclasses.replace(b, dt=b.dt * cap_scale) for b in w.boxes]
+    w.dt_rule, w.dt_factor = 1, factor
+    return w
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_adaptive_time_step_c1(kmc, precision):
+    """The adaptive step of Section 1 (dt = dx / v_max, capped by the box
+    dt), recomputed on the device every step."""
+    w = _adaptive(I.c1_small(steps=8), 1.0, 100.0)
+    run_parity(kmc, w, 8, precision=precision)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_adaptive_time_step_batch_and_sphere(kmc, precision):
+    w = _adaptive(I.c4_batch(nboxes=12, n_lo=100, n_hi=4000, steps=4), 0.5, 10.0)
+    run_parity(kmc, w, 4, precision=precision, use_graph=True)
+    w = _adaptive(I.c3_sphere(n=150_000, steps=3), 0.3, 10.0)
+    run_parity(kmc, w, 3, precision=precision, block_size=128)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_full_neighbourhood_search_mode(kmc, precision):
+    """KMC_SEARCH_FULL (running minimum over the whole neighbourhood, no
+    candidate lists) gives the oracle's result on every workload shape."""
+    cases = [(I.c1_small(steps=4), 4), (I.c2_shock(n=40_000, steps=5), 5), (I.c3_sphere(n=150_000, steps=2), 2),
+             (I.c4_batch(nboxes=12, n_lo=100, n_hi=4000, steps=2), 2), (I.c5_blobs(n=60_000, steps=2), 2)]
+    for w, steps in cases:
+        run_parity(kmc, w, steps, precision=precision, search_mode=kmc.KMC_SEARCH_FULL)
+    assert run_parity.last_stats["rechecks"] == 0 and run_parity.last_stats["fallbacks"] == 0
+
+
+def test_autotune_launch_and_cells(kmc):
+    """kmc_autotune times every candidate; its launch choice leaves the
+    results unchanged, and a tuned cell grid is a different (valid) grid that
+    the oracle reproduces when given the same boxes."""
+    w = I.c5_blobs(n=60_000, steps=2)
+    boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0", flags=kmc.KMC_TUNE_LAUNCH, steps=2,
+                                   seed=w.seed, precision=kmc.KMC_FP32_SCREEN)
+    print(f"\n[tune] launch: {cfg['search_mode']}/{cfg['block_size']} "
+          f"{[round(t['ms_per_step'], 3) for t in tun['tried']]}", flush=True)
+    assert boxes == w.boxes and len(tun["tried"]) == 6
+    assert all(np.isfinite(t["ms_per_step"]) for t in tun["tried"])
+    best = tun["tried"][tun["best"]]
+    assert best["ms_per_step"] == min(t["ms_per_step"] for t in tun["tried"])
+    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
+
+    boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0",
+                                   flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_CELLS, steps=2,
+                                   seed=w.seed, precision=kmc.KMC_FP32_SCREEN)
+    best = tun["tried"][tun["best"]]
+    print(f"[tune] cells: kappa {best['kappa']} grid {boxes[0].ncell} "
+          f"{cfg['search_mode']}/{cfg['block_size']}", flush=True)
+    assert len(tun["tried"]) == 24
+    assert boxes[0] == kmc.box_with_kappa(w.boxes[0], best["kappa"])
+    w.boxes = boxes
+    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])

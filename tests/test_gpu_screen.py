@@ -86,13 +86,15 @@ def gpu_vs_oracle(kmc, w, precision, steps=1, **cfg):
     return mism, same_state, stats
 
 
+@pytest.mark.parametrize("mode", ["half", "full"])
 @pytest.mark.parametrize("variant", [dict(), dict(bulk=20.0), dict(origin=1000.0), dict(bulk=5.0, origin=-300.0)])
-def test_screen_exact_on_adversarial_pairs(kmc, variant):
+def test_screen_exact_on_adversarial_pairs(kmc, variant, mode):
     w = adversarial(seed=11, **variant)
-    print(f"\n[screen] adversarial {variant} N={w.n}", flush=True)
-    mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    print(f"\n[screen] adversarial {variant} N={w.n} search={mode}", flush=True)
+    mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2, search_mode=sm)
     assert mism64 == 0 and st64
-    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2)
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
     print(f"[screen] mismatches={mism} candidates fp32={stats['candidates']} fp64={s64['candidates']}",
           flush=True)
     assert mism == 0 and same
@@ -100,14 +102,16 @@ def test_screen_exact_on_adversarial_pairs(kmc, variant):
     assert stats["candidates"] >= s64["candidates"]
 
 
-def test_negative_control_without_error_bounds(kmc):
+@pytest.mark.parametrize("mode", ["half", "full"])
+def test_negative_control_without_error_bounds(kmc, mode):
     """With the error bounds disabled the FP32 screen decides near-boundary
     pairs from FP32 values alone and must disagree with the oracle."""
     w = adversarial(seed=12, kinds=("radius", "tend", "tzero"))
-    mism, _, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, guard_scale=-1.0)
-    print(f"\n[screen] guard off: mismatches={mism} rechecks={stats['rechecks']}", flush=True)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    mism, _, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, guard_scale=-1.0, search_mode=sm)
+    print(f"\n[screen] guard off ({mode}): mismatches={mism} rechecks={stats['rechecks']}", flush=True)
     assert mism > 0
-    mism_on, _, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN)
+    mism_on, _, _ = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, search_mode=sm)
     assert mism_on == 0
 
 
@@ -140,6 +144,10 @@ def test_candidate_overflow_paths(kmc, precision):
     mism, same, stats = gpu_vs_oracle(kmc, w, prec, recheck_capacity=1, use_graph=True, steps=2)
     assert mism == 0 and same
     assert stats["fallbacks"] == 2
+    # the full-neighbourhood search needs neither
+    mism, same, stats = gpu_vs_oracle(kmc, w, prec, steps=2, search_mode=kmc.KMC_SEARCH_FULL)
+    assert mism == 0 and same
+    assert stats["rechecks"] == 0 and stats["fallbacks"] == 0
 
 
 @pytest.mark.parametrize("guard", [1.0, 16.0])

@@ -12,7 +12,7 @@
 * c2_shock (N = 1e6, 19.5 M cells) and c4_batch (256 boxes, ~5e6 particles)
   are compared with full oracle steps.
 * c5_blobs (N = 1e7, ~3e10 pair tests per step) is checked at sampled
-  particles, both precisions.
+  particles, both precisions and both search organisations.
 """
 import numpy as np
 import pytest
@@ -109,11 +109,13 @@ def test_c3_sphere_1e8_sampled_and_paths_identical(kmc):
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.parametrize("mode", ["half", "full"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_c5_blobs_1e7_sampled(kmc, precision):
+def test_c5_blobs_1e7_sampled(kmc, precision, mode):
     w = I.c5_blobs(steps=1)
     prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
-    run_sampled(kmc, w, prec, 2000, seed=5)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    run_sampled(kmc, w, prec, 2000, seed=5, search_mode=sm)
 
 
 def full_oracle(kmc, w, steps, precision):

@@ -483,3 +483,68 @@ def test_sampled_step_equals_full_step(name):
     assert np.array_equal(st, s1[:, sel])
     with pytest.raises(ValueError):
         O.step_sampled(box, s0, ids, 7, np.array([n]), seed=w.seed)
+
+
+# --------------------------------------------------------------------------
+# Adaptive time step (Section 1: dt = bin width / largest speed)
+# --------------------------------------------------------------------------
+
+def _adt_box(n, ncell=(32, 32, 32), lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), dt=1.0):
+    return I.Box(n=n, lo=lo, hi=hi, ncell=ncell, periodic=(True,) * 3, D2=1e-6, dt=dt)
+
+
+def test_adaptive_dt_closed_forms():
+    # speeds 13 (3-4-12 triangle) and smaller: dt = (1/32) / 13, one rounding
+    s = np.zeros((6, 3))
+    s[3:6, 0] = (3.0, -4.0, 12.0)
+    s[3:6, 1] = (1.0, 1.0, 1.0)
+    s[3:6, 2] = (-5.0, 0.0, 0.0)
+    assert O.adaptive_dt(_adt_box(3), s) == 2.0 ** -5 / 13.0
+    assert O.adaptive_dt(_adt_box(3), s, factor=0.5) == 2.0 ** -6 / 13.0
+    # the smallest bin width of an anisotropic grid: (2 - 0) / 80 = 1/40
+    b = _adt_box(3, ncell=(32, 80, 32), hi=(1.0, 2.0, 1.0))
+    assert O.adaptive_dt(b, s) == 0.025 / 13.0
+    # capped by the box dt, and the cap when everything is at rest
+    assert O.adaptive_dt(_adt_box(3, dt=1e-4), s) == 1e-4
+    assert O.adaptive_dt(_adt_box(3, dt=0.5), np.zeros((6, 3))) == 0.5
+    assert O.adaptive_dt(_adt_box(0, dt=0.5), np.zeros((6, 0))) == 0.5
+
+
+def test_adaptive_dt_keeps_particles_in_their_neighbourhood():
+    """With dt = dx / v_max no particle moves more than one bin width in a
+    step (the purpose the paper gives for the rule)."""
+    rng = np.random.default_rng(21)
+    n = 20000
+    s = np.empty((6, n))
+    s[0:3] = rng.random((3, n))
+    s[3:6] = rng.standard_normal((3, n)) * rng.uniform(0.1, 3.0)
+    box = I.Box(n=n, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(40, 40, 40), periodic=(False,) * 3,
+                D2=1e-12, dt=1.0)
+    dt = O.adaptive_dt(box, s)
+    speed = np.sqrt((s[3:6] ** 2).sum(axis=0))
+    assert speed.max() * dt <= 0.025 * (1 + 1e-14)
+    assert speed.max() * dt >= 0.025 * (1 - 1e-14)
+    w = I.Workload("adt", [box], s.copy(), 1, dt_rule=1)
+    r = O.Run(w)
+    r.step()
+    st = r.full_state()
+    # reflecting walls mirror; the distance to the mirrored start is bounded too
+    inside = (s[0:3] > 0.03).all(axis=0) & (s[0:3] < 0.97).all(axis=0)
+    moved = np.sqrt(((st[0:3, inside] - s[0:3, inside]) ** 2).sum(axis=0))
+    assert moved.max() <= 0.025 * (1 + 1e-12)
+    assert r.dt_last[0] == dt and r.time[0] == dt
+
+
+def test_adaptive_dt_run_accumulates_time_per_box():
+    w = I.c4_batch(nboxes=3, n_lo=200, n_hi=400, steps=3)
+    w.dt_rule = 1
+    r = O.Run(w)
+    tot = [0.0] * 3
+    for _ in range(3):
+        states = [s.copy() for s in r.state]
+        r.step()
+        for b, box in enumerate(w.boxes):
+            dt = O.adaptive_dt(box, states[b])
+            assert r.dt_last[b] == dt and dt <= box.dt
+            tot[b] += dt
+    assert r.time == tot
