@@ -168,6 +168,47 @@ def cpu_baseline(name, n_sample):
                 cpu=platform.processor() or platform.machine())
 
 
+def ppc_sweep(kmc, args):
+    """Wall time per step and per unit of simulated time against particles
+    per cell at N = 1e8 (the study of Section 2, Fig. 1, on one GPU)."""
+    import torch
+    from paper_1310_3437_amd import inputs
+    n = int(args.n) if args.n else 100_000_000
+    state = None
+    rows = []
+    for ppc in (3, 4, 6, 8, 12, 16, 24):
+        w = inputs.ppc_sweep_case(n=n, ppc=ppc, state=state)
+        state = w.state
+        # with dt = dx / v_max every particle has ~10^2 acceptable partners
+        # per step (mean free path far below the cell edge): the
+        # full-neighbourhood search is the organisation for this regime
+        for mode in ("full",):
+            sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+            log(f"[sweep] ppc {w.info['ppc']:.2f} cells {w.boxes[0].ncell[0]}^3 search {mode}")
+            sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=kmc.KMC_FP32_SCREEN,
+                          dt_rule=1, dt_factor=1.0, search_mode=sm, history=64)
+            sim.step(args.warmup)
+            torch.cuda.synchronize()
+            dt0, t0_sim = sim.time()
+            t0 = time.perf_counter()
+            sim.step(args.steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            dt1, t1_sim = sim.time()
+            tests = sim.pair_tests()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            ms = 1e3 * el / args.steps
+            rows.append(dict(ppc=w.info["ppc"], cells=w.boxes[0].ncell[0], search=mode, ms_per_step=ms,
+                             dt=float(dt1[0]), wall_s_per_unit_time=el / float(t1_sim[0] - t0_sim[0]),
+                             pair_tests_per_step=tests))
+            log(f"[sweep]   {ms:.2f} ms/step, dt {dt1[0]:.3e}, {rows[-1]['wall_s_per_unit_time']:.3f} s per unit time")
+    print(json.dumps({"sweep": "ppc", "N": n, "precision": "fp32_screen", "steps": args.steps,
+                      "workload": "periodic unit cube, one speed (1), random directions, D=(3/N)^(1/3), "
+                                  "adaptive dt = dx/v_max", "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +222,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=None)
     ap.add_argument("--paths", default="fp64,fp32")
+    ap.add_argument("--ppc-sweep", action="store_true",
+                    help="wall time against particles per cell (Fig. 1 study) instead of the benchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -194,6 +237,9 @@ def main():
     kmc.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.ppc_sweep:
+        ppc_sweep(kmc, args)
+        return
     full = dict(c3_sphere=1e8, c2_shock=1e6, c4_batch=None, c5_blobs=1e7)
     sample = dict(c3_sphere=1e7, c2_shock=1e6, c4_batch=None, c5_blobs=3e5)
     if args.workload not in full:

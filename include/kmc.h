@@ -118,7 +118,16 @@ typedef struct kmc_config {
     int32_t profile;           /* 1: time every phase with HIP events (disables graphs)  */
     int32_t dt_rule;           /* kmc_dt_rule (see below)                                */
     int32_t search_mode;       /* kmc_search_mode                                        */
-    int32_t reserved[3];       /* must be zero                                           */
+    int32_t dims;              /* 3 (or 0): space.  2: planar mode (Section 1 also runs
+                                  the method in two dimensions, with 9 neighbouring
+                                  bins): every box must have ncell[2] = 1, bc[2] =
+                                  REFLECT and geometry BOX, the caller keeps z and vz
+                                  constant (vz = 0), and the scatter direction is
+                                  uniform in the x-y plane: from the first (e1, e2)
+                                  with 0 < s = e1*e1 + e2*e2 < 1 of the same random
+                                  numbers, n = ((e1*e1 - e2*e2) / s,
+                                  ((2*e1)*e2) / s, 0)                                    */
+    int32_t reserved[2];       /* must be zero                                           */
     double guard_scale;        /* FP32 screen: factor applied to the derived rounding-error
                                   bounds; 0 = 4 (default), >= 1 otherwise.  -1 disables the
                                   bounds (testing only: the screen is then not exact)     */

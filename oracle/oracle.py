@@ -24,6 +24,7 @@ class OrcBox(C.Structure):
         ("periodic", C.c_int32 * 3),
         ("ncell", C.c_int32 * 3),
         ("kinematics", C.c_int32),
+        ("dims", C.c_int32),
         ("lo", C.c_double * 3),
         ("hi", C.c_double * 3),
         ("inv_h", C.c_double * 3),
@@ -66,6 +67,8 @@ def lib():
         L.orc_philox4x64_10.restype = None
         L.orc_direction.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, dp]
         L.orc_direction.restype = None
+        L.orc_direction2.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, dp]
+        L.orc_direction2.restype = None
         L.orc_pair_hash.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_pair_hash.restype = C.c_uint64
         L.orc_step.argtypes = [bp, dp, u32p, C.c_uint64, i32p, u64p, u64p, C.c_int, u64p]
@@ -86,7 +89,7 @@ def _ptr(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def make_box(box, seed=1, kinematics=0):
+def make_box(box, seed=1, kinematics=0, dims=3):
     """OrcBox from a paper_1310_3437_amd.inputs.Box (or any object with the
     same attributes)."""
     ob = OrcBox()
@@ -99,6 +102,7 @@ def make_box(box, seed=1, kinematics=0):
         ob.hi[k] = float(box.hi[k])
         ob.inv_h[k] = float(box.inv_h[k])
     ob.kinematics = int(kinematics)
+    ob.dims = int(dims)
     ob.R = float(box.R)
     ob.D2 = float(box.D2)
     ob.dt = float(box.dt)
@@ -177,9 +181,10 @@ def philox(ctr, key):
     return [int(x) for x in o]
 
 
-def direction(seed, step, a):
+def direction(seed, step, a, dims=3):
     o = np.zeros(3, dtype=np.float64)
-    lib().orc_direction(int(seed), int(step), int(a), _ptr(o, C.c_double))
+    f = lib().orc_direction2 if dims == 2 else lib().orc_direction
+    f(int(seed), int(step), int(a), _ptr(o, C.c_double))
     return o
 
 
@@ -199,7 +204,7 @@ def adaptive_dt(box, state, factor=1.0):
     return float(out.value)
 
 
-def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0):
+def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, dims=3):
     """The oracle step of one box evaluated at the particles `sel` only
     (indices into the box); `state` is not modified.  Returns (partner
     indices of the selected particles, their (6, len(sel)) post-step state)."""
@@ -207,7 +212,7 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0):
     n = s.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
-    ob = make_box(box, seed=seed, kinematics=kinematics)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims)
     ob.n = n
     partner = np.empty(len(sel), dtype=np.int32)
     out = np.empty((len(sel), 6), dtype=np.float64)
@@ -219,13 +224,13 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0):
     return partner, out.T.copy()
 
 
-def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0):
+def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3):
     """One oracle step of one box, in place on `state` ((6, n) float64,
     C-contiguous).  Returns (partner indices, npairs, digest, pair_tests)."""
     assert state.dtype == np.float64 and state.flags.c_contiguous and state.shape[0] == 6
     n = state.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
-    ob = make_box(box, seed=seed, kinematics=kinematics)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims)
     ob.n = n
     partner = np.empty(n, dtype=np.int32)
     npairs = C.c_uint64(0)
@@ -272,6 +277,7 @@ class Run:
             self.time[b] += float(box.dt)
             p, npairs, dig, t = step_box(box, self.state[b], self.ids[b], self.step_index,
                                          seed=self.w.seed, kinematics=self.w.kinematics,
+                                         dims=getattr(self.w, "dims", 3),
                                          nthreads=self.nthreads)
             ids = self.ids[b]
             has = p >= 0

@@ -37,6 +37,8 @@ static int box_ok(const orc_box* b)
         if (b->sphere && b->periodic[k]) return 0;
     }
     if (b->sphere && !(b->R > 0.0)) return 0;
+    if (b->dims != 0 && b->dims != 2 && b->dims != 3) return 0;
+    if (b->dims == 2 && (b->ncell[2] != 1 || b->periodic[2] || b->sphere)) return 0;
     return 1;
 }
 
@@ -387,6 +389,33 @@ void orc_direction(uint64_t seed, uint64_t step, uint32_t a, double n[3])
 }
 
 /* SplitMix64 output function of the packed pair (a << 32 | b). */
+/* Planar mode (Section 1 also runs the method in two dimensions): a point
+ * (e1, e2) uniform in the unit disk has a uniform polar angle phi, and
+ * ((e1^2 - e2^2), 2 e1 e2) / (e1^2 + e2^2) = (cos 2phi, sin 2phi) is then a
+ * uniform direction; same random numbers and rejection as in space. */
+void orc_direction2(uint64_t seed, uint64_t step, uint32_t a, double n[3])
+{
+    const uint64_t key[2] = {seed, 0};
+    for (uint64_t blk = 0; blk < 32; ++blk) {
+        const uint64_t ctr[4] = {blk, (uint64_t)a, step, 0};
+        uint64_t w[4];
+        orc_philox4x64_10(ctr, key, w);
+        for (int t = 0; t < 2; ++t) {
+            double e1 = 2.0 * ((double)(w[2 * t] >> 11) * 0x1.0p-53) - 1.0;
+            double e2 = 2.0 * ((double)(w[2 * t + 1] >> 11) * 0x1.0p-53) - 1.0;
+            double a1 = e1 * e1, a2 = e2 * e2;
+            double s = a1 + a2;
+            if (s > 0.0 && s < 1.0) {
+                n[0] = (a1 - a2) / s;
+                n[1] = ((2.0 * e1) * e2) / s;
+                n[2] = 0.0;
+                return;
+            }
+        }
+    }
+    n[0] = 1.0; n[1] = 0.0; n[2] = 0.0;
+}
+
 uint64_t orc_pair_hash(uint32_t a, uint32_t b)
 {
     uint64_t z = (((uint64_t)a << 32) | (uint64_t)b) + 0x9E3779B97F4A7C15ULL;
@@ -486,7 +515,8 @@ static void collide_pair(const orc_box* b, const double* s, const uint32_t* ids,
     orc_pair(b, pa, pc, wrap, &q);
     *tstar = (-q.b) / q.g2;
     double nhat[3];
-    orc_direction(b->seed, step, ids[a], nhat);
+    if (b->dims == 2) orc_direction2(b->seed, step, ids[a], nhat);
+    else orc_direction(b->seed, step, ids[a], nhat);
     double hg = 0.5 * sqrt(q.g2);
     for (int k = 0; k < 3; ++k) {
         double vcm = 0.5 * (pa[3 + k] + pc[3 + k]);

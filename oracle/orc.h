@@ -47,6 +47,9 @@ typedef struct {
     int32_t  periodic[3];  /* per axis: 1 periodic, 0 reflecting planes lo/hi     */
     int32_t  ncell[3];     /* bins per axis                                     */
     int32_t  kinematics;   /* 0: scatter executed at t*, 1: velocity-only update */
+    int32_t  dims;         /* 3 (or 0): space; 2: planar mode (one bin along z,
+                              no periodic z, no sphere; isotropic scatter in the
+                              x-y plane; z and vz stay as given)              */
     double   lo[3], hi[3]; /* box (and bin grid) bounds                         */
     double   inv_h[3];     /* ncell[k] / (hi[k] - lo[k]), supplied by the caller */
     double   R;            /* sphere radius (sphere == 1)                       */
@@ -87,6 +90,9 @@ void orc_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t ou
 
 /* Isotropic unit vector for the pair whose smaller id is a, at step `step`. */
 void orc_direction(uint64_t seed, uint64_t step, uint32_t a, double n[3]);
+
+/* Planar variant: uniformly distributed unit vector in the x-y plane. */
+void orc_direction2(uint64_t seed, uint64_t step, uint32_t a, double n[3]);
 
 /* 64-bit hash of an unordered pair (a < b), used for the per-step digest. */
 uint64_t orc_pair_hash(uint32_t a, uint32_t b);

@@ -72,6 +72,7 @@ int check_cfg(const kmc_config& c)
         return KMC_EINVAL;
     if (c.dt_rule != KMC_DT_FIXED && c.dt_rule != KMC_DT_ADAPTIVE) return KMC_EINVAL;
     if (c.search_mode != KMC_SEARCH_HALF && c.search_mode != KMC_SEARCH_FULL) return KMC_EINVAL;
+    if (c.dims != 0 && c.dims != 2 && c.dims != 3) return KMC_EINVAL;
     if (c.dt_factor != 0.0 && !finite_pos(c.dt_factor)) return KMC_EINVAL;
     for (int r : c.reserved)
         if (r != 0) return KMC_EINVAL;
@@ -102,6 +103,10 @@ int validate(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, Total
     }
     int rc = check_cfg(*cfg);
     if (rc != KMC_OK) return rc;
+    if (cfg->dims == 2)
+        for (uint32_t b = 0; b < nboxes; ++b)
+            if (boxes[b].ncell[2] != 1 || boxes[b].bc[2] != KMC_BC_REFLECT || boxes[b].geometry != KMC_GEOM_BOX)
+                return KMC_EINVAL;
     return totals(boxes, nboxes, t);
 }
 
@@ -139,8 +144,10 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.slot = (uint32_t*)take(4 * N);
     p.partner = (int32_t*)take(4 * N);
     p.sl_cnt = (uint32_t*)take(4 * N);
-    p.sl_first = (uint32_t*)take(4 * N);
-    p.sl_idx = (uint32_t*)take(4 * N * (kSlots - 1));
+    p.sl_idx = (uint32_t*)take(4 * N * kSlots);
+    p.sl_key = (double*)take(8 * N * kSlots);
+    p.fb_key = (double*)take(8 * N);
+    p.fb_j = (int32_t*)take(4 * N);
     p.boxidx = nboxes > 1 ? (uint32_t*)take(4 * N) : nullptr;
     p.count = (uint32_t*)take(4 * C);
     p.start = (uint32_t*)take(4 * (C + 1));
@@ -163,6 +170,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.guard = cfg.guard_scale > 0.0 ? (float)cfg.guard_scale : (cfg.guard_scale < 0.0 ? 0.0f : 4.0f);
     p.dt_rule = cfg.dt_rule;
     p.search_mode = cfg.search_mode;
+    p.dims = cfg.dims == 2 ? 2 : 3;
     p.dt_factor = cfg.dt_factor != 0.0 ? cfg.dt_factor : 1.0;
     return off;
 }

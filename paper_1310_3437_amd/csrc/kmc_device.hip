@@ -85,7 +85,7 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 // candidate points (words 0,1 and 2,3) e = 2 (w >> 11) 2^-53 - 1 in [-1, 1);
 // the first with 0 < s = e1^2 + e2^2 < 1 gives
 // n = (2 e1 sqrt(1-s), 2 e2 sqrt(1-s), 1 - 2s).
-__device__ void direction(uint64_t seed, uint64_t step, uint32_t a, double n[3])
+__device__ void direction(uint64_t seed, uint64_t step, uint32_t a, double n[3], int dims)
 {
     for (uint64_t blk = 0; blk < 32; ++blk) {
         uint64_t w[4] = {blk, (uint64_t)a, step, 0};
@@ -94,17 +94,31 @@ __device__ void direction(uint64_t seed, uint64_t step, uint32_t a, double n[3])
         for (int t = 0; t < 2; ++t) {
             double e1 = 2.0 * ((double)(w[2 * t] >> 11) * 0x1.0p-53) - 1.0;
             double e2 = 2.0 * ((double)(w[2 * t + 1] >> 11) * 0x1.0p-53) - 1.0;
-            double s = e1 * e1 + e2 * e2;
-            if (s > 0.0 && s < 1.0) {
-                double f = 2.0 * sqrt(1.0 - s);
-                n[0] = e1 * f;
-                n[1] = e2 * f;
-                n[2] = 1.0 - 2.0 * s;
-                return;
+            if (dims == 2) {
+                // planar: (cos 2phi, sin 2phi) of a point uniform in the unit disk
+                const double a1 = e1 * e1, a2 = e2 * e2;
+                const double s = a1 + a2;
+                if (s > 0.0 && s < 1.0) {
+                    n[0] = (a1 - a2) / s;
+                    n[1] = ((2.0 * e1) * e2) / s;
+                    n[2] = 0.0;
+                    return;
+                }
+            } else {
+                double s = e1 * e1 + e2 * e2;
+                if (s > 0.0 && s < 1.0) {
+                    double f = 2.0 * sqrt(1.0 - s);
+                    n[0] = e1 * f;
+                    n[1] = e2 * f;
+                    n[2] = 1.0 - 2.0 * s;
+                    return;
+                }
             }
         }
     }
-    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    n[0] = dims == 2 ? 1.0 : 0.0;
+    n[1] = 0.0;
+    n[2] = dims == 2 ? 0.0 : 1.0;
 }
 
 // SplitMix64 output of the packed pair (a << 32 | b): the digest term.
@@ -598,44 +612,54 @@ __device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64&
     }
 }
 
-// Flag on a recorded candidate index: the FP32 screen proved the pair
-// acceptable in FP64 (particle indices stay below 2^31).
-constexpr uint32_t kSureBit = 0x80000000u;
-constexpr uint32_t kIdxMask = 0x7FFFFFFFu;
-
-// Slot k of particle i's candidate list (slot 0 lives in a dense array: most
-// particles have at most one candidate).
-__device__ __forceinline__ uint32_t* slot_ptr(const Plan& p, uint32_t i, uint32_t k)
+// Candidate lists: per particle a count and up to kSlots entries (sorted
+// index of the other particle and the pair's FP64 key c2/g2, which is the
+// same from both sides); entry k of particle i lives at [k * N + i].
+__device__ __forceinline__ void post_candidate(const Plan& p, uint32_t i, uint32_t j, double key)
 {
-    return k == 0 ? p.sl_first + i : p.sl_idx + (size_t)i * (kSlots - 1) + (k - 1);
+    const uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
+    if (k < (uint32_t)kSlots) {
+        p.sl_idx[(size_t)k * p.N + i] = j;
+        p.sl_key[(size_t)k * p.N + i] = key;
+    }
 }
 
-// Record the unordered pair {i, j} in the candidate lists of both; jf is j
-// with the screen's flag bit, which both entries carry.
-__device__ __forceinline__ void record_pair(const Plan& p, uint32_t i, uint32_t jf)
+// The definition's exact FP64 decision for the pair (i, j) seen from i (the
+// image from the two cells), and its key when acceptable.
+__device__ __forceinline__ bool exact_key(const Plan& p, const BoxDev& B, const P64& me, uint32_t j, double& key)
 {
-    const uint32_t j = jf & kIdxMask, flag = jf & kSureBit;
-    uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
-    if (k < (uint32_t)kSlots) *slot_ptr(p, i, k) = jf;
-    k = atomicAdd(&p.sl_cnt[j], 1u);
-    if (k < (uint32_t)kSlots) *slot_ptr(p, j, k) = i | flag;
+    const P64 q = p.B[j];
+    double r[3];
+    rel64(B, me, q, r);
+    const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+    if (!accept(pq, B.D2, B.dt)) return false;
+    key = pq.c2 / pq.g2;
+    return true;
 }
 
 // Pairs a lane found, kept in registers until the end of the wave's search
-// (a global atomic inside the search loop would stall the whole wave); a
-// lane that finds more appends the excess to the step's overflow pair list
-// (one counter, distributed by k_distribute_overflow), or raises the
-// overflow flag when that list is full (whole-step FP64 fallback).
+// (a global atomic or a division inside the search loop would stall the
+// whole wave); a lane that finds more appends the excess to the step's
+// overflow pair list (one counter, handled by k_distribute_overflow), or
+// raises the overflow flag when that list is full (whole-step FP64
+// fallback).
 constexpr int kReg = 4;
+
+__device__ __forceinline__ uint32_t wcode(int wx, int wy, int wz)
+{
+    return (uint32_t)(wx + 1) | ((uint32_t)(wy + 1) << 2) | ((uint32_t)(wz + 1) << 4);
+}
 
 struct Found {
     uint32_t j[kReg];
+    uint32_t w;   // image shift of pair k in bits 6k..6k+5: (wx+1) | (wy+1) << 2 | (wz+1) << 4
     int n;
-    __device__ __forceinline__ void add(const Plan& p, uint32_t i, uint32_t jj)
+    __device__ __forceinline__ void add(const Plan& p, uint32_t i, uint32_t jj, uint32_t wcode)
     {
         if (n < kReg) {
 #pragma unroll
             for (int k = 0; k < kReg; ++k) j[k] = (n == k) ? jj : j[k];
+            w |= wcode << (6 * n);
             ++n;
         } else {
             const uint32_t idx = atomicAdd(&p.ctl->ovf_count, 1u);
@@ -643,20 +667,60 @@ struct Found {
             else atomicOr(&p.ctl->overflow, 1u);
         }
     }
-    // append the kept pairs to both candidate lists
-    __device__ __forceinline__ void flush(const Plan& p, uint32_t i)
+    // Decide the kept pairs exactly in FP64 (the FP32 screen keeps pairs it
+    // could not reject), write i's best among them (its forward best) and
+    // post each acceptable pair to the other particle's list.  The image
+    // shift is the one the search used (that of the two cells).  All lanes
+    // take the same branch-free path: loads first, then the arithmetic,
+    // then the posts.  Returns the number of pairs examined (statistics).
+    template <int BATCH>
+    __device__ __forceinline__ uint32_t flush(const Plan& p, uint32_t i, const P64& me, const BoxDev& B)
     {
-        if (n == 0) return;
-        const uint32_t base = atomicAdd(&p.sl_cnt[i], (unsigned int)n);
+        double key[kReg];
+        bool acc[kReg];
+        // BATCH records in flight at a time (register budget of the search)
 #pragma unroll
-        for (int k = 0; k < kReg; ++k) {
-            if (k < n) {
-                if (base + k < (uint32_t)kSlots) *slot_ptr(p, i, base + k) = j[k];
-                const uint32_t jj = j[k] & kIdxMask;
-                const uint32_t q = atomicAdd(&p.sl_cnt[jj], 1u);
-                if (q < (uint32_t)kSlots) *slot_ptr(p, jj, q) = i | (j[k] & kSureBit);
+        for (int h = 0; h < kReg; h += BATCH) {
+            P64 q[BATCH];
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) q[e] = p.B[h + e < n ? j[h + e] : i];
+#pragma unroll
+            for (int e = 0; e < BATCH; ++e) {
+                const int k = h + e;
+                const uint32_t c = w >> (6 * k);
+                const int wx = (int)(c & 3u) - 1, wy = (int)((c >> 2) & 3u) - 1, wz = (int)((c >> 4) & 3u) - 1;
+                double rx = q[e].x - me.x, ry = q[e].y - me.y, rz = q[e].z - me.z;
+                if (wx != 0) rx = rx + (double)wx * B.L[0];
+                if (wy != 0) ry = ry + (double)wy * B.L[1];
+                if (wz != 0) rz = rz + (double)wz * B.L[2];
+                const PairQ pq = pair_q(rx, ry, rz, q[e].vx - me.vx, q[e].vy - me.vy, q[e].vz - me.vz);
+                acc[k] = k < n && accept(pq, B.D2, B.dt);
+                key[k] = acc[k] ? pq.c2 / pq.g2 : __builtin_inf();
             }
         }
+        double best_key = __builtin_inf();
+        int32_t best = -1;
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) {
+            if (acc[k] && (best < 0 || key[k] < best_key ||
+                           (key[k] == best_key && p.idB[j[k]] < p.idB[best]))) {
+                best_key = key[k];
+                best = (int32_t)j[k];
+            }
+        }
+        uint32_t slot[kReg];
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) slot[k] = acc[k] ? atomicAdd(&p.sl_cnt[j[k]], 1u) : (uint32_t)kSlots;
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) {
+            if (slot[k] < (uint32_t)kSlots) {
+                p.sl_idx[(size_t)slot[k] * p.N + j[k]] = i;
+                p.sl_key[(size_t)slot[k] * p.N + j[k]] = key[k];
+            }
+        }
+        p.fb_key[i] = best_key;
+        p.fb_j[i] = best;
+        return (uint32_t)n;
     }
 };
 
@@ -685,6 +749,8 @@ struct Best {
 struct PolF64 {
     static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
     static constexpr bool kScreen = false;
+    static constexpr int kFlushBatch = 2;
+    static constexpr int kWaves = 6;      // waves per SIMD the half search is compiled for
     struct Lds {
         P64 rec[W];
     };
@@ -692,12 +758,14 @@ struct PolF64 {
         P64 me;
     };
     using Group = NoGroup;
-    __device__ static void begin_group(const Plan&, const BoxDev&, Own&, Group&, int, int, int, int, int) {}
+    __device__ static void begin_group(const Plan&, const BoxDev&, Own&, Group&, int, int, int, int, int, uint32_t,
+                                       bool) {}
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         o.me = p.B[i];
         x = o.me.x; y = o.me.y; z = o.me.z;
     }
+    __device__ static P64 self64(const Plan&, uint32_t, const Own& o) { return o.me; }
     __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev&, const Group&,
                                  int, int, int)
     {
@@ -714,7 +782,7 @@ struct PolF64 {
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            if (accept(pq, D2, dt)) f.add(p, i, j);
+            if (accept(pq, D2, dt)) f.add(p, i, j, wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: running (key, id) minimum over the acceptable pairs
@@ -832,18 +900,19 @@ struct alignas(16) Rec32 {
 struct PolF32 {
     static constexpr int W = 160;         // staged records per chunk (5 KiB)
     static constexpr bool kScreen = true;
+    static constexpr int kFlushBatch = 1;
+    static constexpr int kWaves = 6;
     struct Lds {
         Rec32 r[W];
     };
     struct Own {
-        float x, y, z, vx, vy, vz;
-        double X, Y, Z;
+        float x, y, z, vx, vy, vz;   // position relative to the current group's centre
     };
     using Group = ScreenGroup;
+    __device__ static P64 self64(const Plan& p, uint32_t i, const Own&) { return p.B[i]; }
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         const P64 m = p.B[i];
-        o.X = m.x; o.Y = m.y; o.Z = m.z;
         o.vx = (float)m.vx; o.vy = (float)m.vy; o.vz = (float)m.vz;
         x = m.x; y = m.y; z = m.z;
     }
@@ -851,7 +920,7 @@ struct PolF32 {
     // row (gcy, gcz); its neighbourhood spans cells cxf-1..cxl+1, gcy-1..gcy+1,
     // gcz-1..gcz+1 (images included).
     __device__ static void begin_group(const Plan& p, const BoxDev& B, Own& o, Group& g, int cxf, int cxl,
-                                       int gcy, int gcz, int gb)
+                                       int gcy, int gcz, int gb, uint32_t i, bool in)
     {
         const int clo[3] = {cxf - 1, gcy - 1, gcz - 1}, chi[3] = {cxl + 1, gcy + 1, gcz + 1};
 #pragma unroll
@@ -860,9 +929,12 @@ struct PolF32 {
             g.X0[k] = B.lo[k] + 0.5 * (double)(clo[k] + chi[k] + 1) * h;
         }
         g.t = p.box_sb[gb];
-        o.x = (float)(o.X - g.X0[0]);
-        o.y = (float)(o.Y - g.X0[1]);
-        o.z = (float)(o.Z - g.X0[2]);
+        if (in) {
+            const P64 m = p.B[i];
+            o.x = (float)(m.x - g.X0[0]);
+            o.y = (float)(m.y - g.X0[1]);
+            o.z = (float)(m.z - g.X0[2]);
+        }
     }
     // FP32 copy of a candidate: image-shifted position relative to X0 and
     // velocity, each rounded once
@@ -878,7 +950,7 @@ struct PolF32 {
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
-                                const Own& o, const BoxDev& B, const Group& g, int, int, int, Found& f)
+                                const Own& o, const BoxDev& B, const Group& g, int wx, int wy, int wz, Found& f)
     {
         const float D2 = B.D2_32, dt = B.dt_32;
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, tt1 = g.t.tt1, tc0 = g.t.tc0, tc1 = g.t.tc1;
@@ -893,11 +965,7 @@ struct PolF32 {
             const float m2 = fmaf(-dt, g2, -b);
             const float m3 = fmaf(rr - D2, g2, -(b * b));
             const float Tb = fmaf(tb1, g2, tb0), Tt = fmaf(tt1, g2, tt0), Tc = fmaf(tc1, g2, tc0);
-            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) {
-                // certainly acceptable in FP64: recorded with the flag bit
-                const bool sure = (b < -Tb) & (m2 < -Tt) & (m3 < -Tc) & (g2 > fmaf(g.t.tg1, g2, g.t.tg0));
-                f.add(p, i, j | (sure ? kSureBit : 0u));
-            }
+            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) f.add(p, i, j, wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: every pair the screen cannot reject is decided in
@@ -936,12 +1004,12 @@ struct PolF32 {
     }
 };
 
-#ifndef KMC_SEARCH_WAVES_PER_EU
-#define KMC_SEARCH_WAVES_PER_EU 5
-#endif
+// Waves per SIMD the full-neighbourhood search is compiled for (its FP32
+// variant spills at six).
+constexpr int kFullWaves = 5;
 
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KMC_SEARCH_WAVES_PER_EU)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
 void k_search_half(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -963,6 +1031,7 @@ void k_search_half(Plan p)
     }
     Found found;
     found.n = 0;
+    found.w = 0u;
 #pragma unroll
     for (int k = 0; k < kReg; ++k) found.j[k] = 0;
     uint64_t remaining = __ballot(valid);
@@ -979,7 +1048,7 @@ void k_search_half(Plan p)
         const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
-        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb);
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
         // Cells [ca, cb] of a row seen with image shift (wx, wy, wz); each lane
         // tests the sub-range [ls, le) of it (empty when ls >= le).
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
@@ -1032,7 +1101,11 @@ void k_search_half(Plan p)
             }
         }
     }
-    if (valid) found.flush(p, i);
+    uint64_t c = valid ? found.template flush<Pol::kFlushBatch>(p, i, Pol::self64(p, i, own), p.boxes[bidx]) : 0u;
+    // statistics: pairs the search kept, counted at both particles
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], 2ull * (unsigned long long)c);
 }
 
 // Full-neighbourhood variant of the search (KMC_SEARCH_FULL): every
@@ -1042,7 +1115,7 @@ void k_search_half(Plan p)
 // acceptable partners per particle, where the candidate lists of the
 // half-neighbourhood search overflow.  Rows and staging as in k_search_half.
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(KMC_SEARCH_WAVES_PER_EU)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
 void k_search_full(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -1083,7 +1156,7 @@ void k_search_full(Plan p)
         const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
-        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb);
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz) {
             const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];
             const bool sh = (wx | wy | wz) != 0;
@@ -1132,15 +1205,23 @@ void k_search_full(Plan p)
     if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c);
 }
 
-// Pairs beyond a search lane's register slots, into both candidate lists.
+// Pairs beyond a search lane's register slots: decided in FP64 and posted to
+// both candidate lists.
 __global__ void k_distribute_overflow(Plan p)
 {
     const uint32_t cnt = p.ctl->ovf_count;
     const uint32_t n = cnt < p.ovf_cap ? cnt : p.ovf_cap;
     for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
         const uint2 e = p.ovf[k];
-        record_pair(p, e.x, e.y);
+        const P64 me = p.B[e.x];
+        double key;
+        if (exact_key(p, box_of(p, e.x), me, e.y, key)) {
+            post_candidate(p, e.x, e.y, key);
+            post_candidate(p, e.y, e.x, key);
+        }
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n)
+        atomicAdd(&p.cand_acc[0], 2ull * (unsigned long long)n);
 }
 
 // Wave-aggregated append of this lane's particle to the FP64 recheck list
@@ -1161,50 +1242,32 @@ __device__ __forceinline__ void push_recheck(const Plan& p, uint32_t i, bool nee
     }
 }
 
-// Partner of every particle from its recorded candidates: the exact FP64
-// (key, id) minimum over those the definition accepts.  The FP64 search
-// records only acceptable pairs (CHECK = false: a single candidate is the
-// partner); the FP32 screen records every pair it could not reject
-// (CHECK = true: each is tested exactly).  A particle with more candidates
-// than slots is searched again in full.
-template <bool CHECK>
+// Partner of every particle: the (key, id) minimum of its forward best (the
+// pairs its own search lane found) and the entries of its candidate list
+// (pairs found from the other side, or through the overflow list); keys are
+// exact FP64, ids are read only to break equal keys.  A particle with more
+// list entries than slots is searched again in full.
 __global__ __launch_bounds__(256) void k_finish(Plan p)
 {
-    __shared__ uint64_t red[32];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const bool valid = i < p.N;
     const uint32_t cnt = valid ? p.sl_cnt[i] : 0u;
-    int32_t best = -1;
     if (cnt != 0) p.sl_cnt[i] = 0u;
-    const uint32_t first = cnt == 1 ? p.sl_first[i] : 0u;
-    if (cnt == 1 && (!CHECK || (first & kSureBit))) {
-        best = (int32_t)(first & kIdxMask);
-    } else if (cnt >= 1 && cnt <= (uint32_t)kSlots) {
-        const BoxDev& B = box_of(p, i);
-        const P64 me = p.B[i];
-        double best_key = __builtin_inf();
-        uint32_t best_id = 0xFFFFFFFFu;
+    double best_key = valid ? p.fb_key[i] : 0.0;
+    int32_t best = valid ? p.fb_j[i] : -1;
+    if (cnt >= 1 && cnt <= (uint32_t)kSlots) {
         for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t j = *slot_ptr(p, i, k) & kIdxMask;
-            const P64 q = p.B[j];
-            double r[3];
-            rel64(B, me, q, r);
-            const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-            if (CHECK && !accept(pq, B.D2, B.dt)) continue;
-            const double key = pq.c2 / pq.g2;
-            const uint32_t idj = p.idB[j];
-            if (key < best_key || (key == best_key && idj < best_id)) {
+            const uint32_t j = p.sl_idx[(size_t)k * p.N + i];
+            const double key = p.sl_key[(size_t)k * p.N + i];
+            if (best < 0 || key < best_key ||
+                (key == best_key && p.idB[j] < p.idB[best])) {
                 best_key = key;
-                best_id = idj;
                 best = (int32_t)j;
             }
         }
     }
     push_recheck(p, i, cnt > (uint32_t)kSlots);
     if (valid) p.partner[i] = best;
-    uint64_t c64 = cnt, z = 0;
-    block_sum2(c64, z, red);
-    if (threadIdx.x == 0 && c64) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c64);
 }
 
 // FP64 re-search of the particles the screen left undecided.
@@ -1305,7 +1368,7 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
             const PairQ pq = pair_q(r[0], r[1], r[2], g[0], g[1], g[2]);
             const double tstar = (-pq.b) / pq.g2;
             double nh[3];
-            direction(p.seed, p.ctl->step, ida, nh);
+            direction(p.seed, p.ctl->step, ida, nh, p.dims);
             const double hg = 0.5 * sqrt(pq.g2);
             double vn[3];
 #pragma unroll
@@ -1445,8 +1508,7 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     mark(KMC_PHASE_FINISH);
     if (p.N > 0 && !full) {
         k_distribute_overflow<<<256, 256, 0, s>>>(p);
-        if (p.precision == KMC_FP32_SCREEN) k_finish<true><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
-        else k_finish<false><<<blocks_for(p.N, 256), 256, 0, s>>>(p);
+        k_finish<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RECHECK);
     if (p.N > 0 && !full) {

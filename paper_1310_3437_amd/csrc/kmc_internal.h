@@ -87,9 +87,11 @@ struct Plan {
     uint32_t* cell;                // per particle in A order: global cell
     uint32_t* slot;                // per particle in A order: rank inside its cell
     int32_t* partner;              // per sorted particle: sorted index of partner or -1
-    uint32_t* sl_cnt;              // per sorted particle: candidates recorded by the search
-    uint32_t* sl_first;            // per sorted particle: the first of them
-    uint32_t* sl_idx;              // per sorted particle: the next kSlots-1 of them
+    uint32_t* sl_cnt;              // per sorted particle: entries posted to its candidate list
+    uint32_t* sl_idx;              // [kSlots][N]: sorted index of the other particle
+    double* sl_key;                // [kSlots][N]: FP64 key of that pair
+    double* fb_key;                // per sorted particle: key of its forward best (inf: none)
+    int32_t* fb_j;                 // per sorted particle: its forward best (-1: none)
     uint32_t* boxidx;              // per particle: its box (null when there is one box)
     uint32_t* count;               // per cell: particles (zero between steps)
     uint32_t* start;               // per cell + 1: exclusive prefix of count
@@ -110,6 +112,7 @@ struct Plan {
     float guard;                   // FP32 screen: scale of the rounding-error bounds (>= 1)
     int32_t dt_rule;               // kmc_dt_rule
     int32_t search_mode;           // kmc_search_mode
+    int32_t dims;                  // 3, or 2 for the planar mode
     double dt_factor;              // adaptive dt: C in dt = min(cap, C dx / v_max)
 };
 

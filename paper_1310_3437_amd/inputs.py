@@ -71,6 +71,7 @@ class Workload:
     kinematics: int = 0          # 0: scatter at t*, 1: velocity-only
     dt_rule: int = 0             # 0: fixed dt per box, 1: adaptive (box dt is the cap)
     dt_factor: float = 1.0       # adaptive rule: factor C in dt = C dx / v_max
+    dims: int = 3                # 2: planar mode (one cell along z, z and vz fixed)
     info: dict = field(default_factory=dict)
 
     @property
@@ -251,6 +252,47 @@ def c5_blobs(n=10_000_000, nblobs=64, D=None, ic_seed=5, steps=50, seed=1):
               periodic=(True, True, True), D2=D * D, dt=dt)
     return Workload("c5_blobs", [box], s, steps, seed,
                     info=dict(D=D, h=h, nblobs=nblobs, mean_speed=mean_speed))
+
+
+def c1_planar(n=4096, D=0.02, ic_seed=11, steps=10, seed=1):
+    """Planar variant of c1_small: n particles uniform in the periodic unit
+    square (z = 0.5 in a single reflecting cell layer of [0, 1]), 2-D
+    Maxwellian velocities sigma_v = 1 (vz = 0), cells of edge >= D, dt =
+    0.2 h / <|v|> with <|v|> = sqrt(pi / 2) for the 2-D Maxwellian."""
+    rng = np.random.default_rng(ic_seed)
+    s = np.zeros((6, n), dtype=np.float64)
+    s[0:2] = rng.random((2, n))
+    s[2] = 0.5
+    s[3:5] = rng.standard_normal((2, n))
+    nc = _ncell_for(1.0, D)
+    h = 1.0 / nc
+    dt = 0.2 * h / math.sqrt(math.pi / 2.0)
+    box = Box(n=n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), ncell=(nc, nc, 1),
+              periodic=(True, True, False), D2=D * D, dt=dt)
+    return Workload("c1_planar", [box], s, steps, seed=seed, dims=2, info=dict(D=D))
+
+
+def ppc_sweep_case(n=100_000_000, ppc=3.0, speed=1.0, ic_seed=6, seed=1, state=None):
+    """The timing study of Section 2 (Fig. 1): n particles of one speed with
+    random directions, uniform in a periodic unit cube, a fixed interaction
+    diameter D = (3/n)^(1/3) (three particles per cell at the finest grid) and
+    a grid of floor((n/ppc)^(1/3)) cells per side, so that the mean number of
+    particles per cell is about ppc (>= 3).  The time step follows the
+    paper's adaptive rule dt = dx / v_max (the box dt is only its cap).
+    `state` reuses positions and velocities of a previous call."""
+    D = (3.0 / n) ** (1.0 / 3.0)
+    nc = int(math.floor((n / ppc) ** (1.0 / 3.0)))
+    nc = min(nc, int(math.floor(1.0 / D)))
+    if state is None:
+        box, s = uniform_box(n, L=1.0, D=D, sigma_v=speed, periodic=True, ic_seed=ic_seed, ncell=nc,
+                             dt=1.0, same_speed=True)
+    else:
+        s = state
+        box = Box(n=n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), ncell=(nc, nc, nc), periodic=(True,) * 3,
+                  D2=D * D, dt=1.0)
+    w = Workload(f"ppc_sweep_{ppc:g}", [box], s, 1, seed=seed, dt_rule=1, dt_factor=1.0,
+                 info=dict(D=D, ppc=n / nc ** 3))
+    return w
 
 
 CONFIGS = {

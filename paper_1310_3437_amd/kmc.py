@@ -55,7 +55,8 @@ class KmcConfig(C.Structure):
         ("profile", C.c_int32),
         ("dt_rule", C.c_int32),
         ("search_mode", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("dims", C.c_int32),
+        ("reserved", C.c_int32 * 2),
         ("guard_scale", C.c_double),
         ("dt_factor", C.c_double),
     ]
@@ -165,7 +166,7 @@ def make_boxes(boxes):
 
 def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR, history=0,
                 recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0,
-                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF):
+                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF, dims=3):
     c = KmcConfig()
     c.seed = int(seed) & ((1 << 64) - 1)
     c.step0 = int(step0)
@@ -180,6 +181,7 @@ def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR
     c.dt_rule = int(dt_rule)
     c.dt_factor = float(dt_factor)
     c.search_mode = int(search_mode)
+    c.dims = int(dims)
     return c
 
 
@@ -200,11 +202,38 @@ def box_with_kappa(box, kappa):
     return nb
 
 
-def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, **config):
+def _tune_key(boxes, device_name, flags, steps, config):
+    import hashlib
+    import json
+    desc = dict(device=device_name, flags=int(flags), steps=int(steps),
+                config={k: config[k] for k in sorted(config) if k not in ("seed", "step0", "history", "profile",
+                                                                          "use_graph")},
+                boxes=[dict(n=int(b.n), lo=list(map(float, b.lo)), hi=list(map(float, b.hi)),
+                            ncell=list(map(int, b.ncell)), periodic=list(map(bool, b.periodic)),
+                            sphere=bool(b.sphere), R=float(b.R), D2=float(b.D2), dt=float(b.dt)) for b in boxes])
+    return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()
+
+
+def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=None, **config):
     """Run kmc_autotune on `state`; returns (boxes, config dict, tuning dict).
-    The boxes differ from the input only with KMC_TUNE_CELLS."""
+    The boxes differ from the input only with KMC_TUNE_CELLS.  With `cache`
+    (a JSON file path) a previous choice for the same device, boxes, flags
+    and configuration is reused without timing, so repeated runs make the
+    same choice."""
+    import json
     import torch
     boxes = list(boxes)
+    key = None
+    if cache is not None:
+        key = _tune_key(boxes, torch.cuda.get_device_name(torch.device(device)), flags, steps, config)
+        if os.path.exists(cache):
+            with open(cache) as fh:
+                hit = json.load(fh).get(key)
+            if hit is not None:
+                kappa = hit["kappa"]
+                nb = [box_with_kappa(b, kappa) for b in boxes] if kappa > 0 else boxes
+                return nb, dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"]), \
+                    dict(best=hit["best"], tried=hit["tried"], cached=True)
     cfg = make_config(**config)
     arr = make_boxes(boxes)
     st = torch.as_tensor(state, dtype=torch.float64).to(device).contiguous()
@@ -224,7 +253,20 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, **conf
     new_cfg = dict(config, search_mode=int(out_c.search_mode), block_size=int(out_c.block_size))
     tried = [dict(ms_per_step=tun.ms_per_step[k], search_mode=tun.search_mode[k], block_size=tun.block_size[k],
                   kappa=tun.kappa[k]) for k in range(tun.ntried)]
-    return new_boxes, new_cfg, dict(best=int(tun.best), tried=tried)
+    if cache is not None:
+        db = {}
+        if os.path.exists(cache):
+            with open(cache) as fh:
+                db = json.load(fh)
+        best = tried[int(tun.best)]
+        db[key] = dict(search_mode=best["search_mode"], block_size=best["block_size"], kappa=best["kappa"],
+                       best=int(tun.best), tried=[{k: (None if isinstance(v, float) and v != v else v)
+                                                   for k, v in t.items()} for t in tried])
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(db, fh, indent=1)
+        os.replace(tmp, cache)
+    return new_boxes, new_cfg, dict(best=int(tun.best), tried=tried, cached=False)
 
 
 def workspace_bytes(boxes, config):

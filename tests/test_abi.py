@@ -80,7 +80,7 @@ def test_invalid_boxes_rejected(mutate):
 @pytest.mark.parametrize("cfg", [
     dict(precision=7), dict(kinematics=3), dict(block_size=100), dict(block_size=2048),
     dict(dt_rule=2), dict(dt_rule=1, dt_factor=-1.0), dict(dt_rule=1, dt_factor=float("inf")),
-    dict(search_mode=2), dict(search_mode=-1),
+    dict(search_mode=2), dict(search_mode=-1), dict(dims=1), dict(dims=4),
 ])
 def test_invalid_configs_rejected(cfg):
     assert _ws([_good()], **cfg)[0] == kmc.KMC_EINVAL
@@ -89,7 +89,7 @@ def test_invalid_configs_rejected(cfg):
 def test_reserved_config_words_must_be_zero():
     arr = kmc.make_boxes([_good()])
     c = kmc.make_config()
-    c.reserved[2] = 1
+    c.reserved[1] = 1
     n = C.c_size_t(0)
     assert kmc.load().kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
 
@@ -126,3 +126,13 @@ def test_box_with_kappa_grid():
     kmc.box_with_kappa(small, 1.0)              # 3 cells: allowed
     with pytest.raises(kmc.KmcError):
         kmc.box_with_kappa(small, 1.25)         # 2 cells on a periodic axis
+
+
+def test_planar_mode_needs_one_reflecting_z_layer():
+    w = I.c1_planar()
+    assert _ws(w.boxes, dims=2)[0] == 0
+    b = I.c1_small().boxes[0]                   # 30 cells along z
+    assert _ws([b], dims=2)[0] == kmc.KMC_EINVAL
+    import dataclasses
+    per = dataclasses.replace(w.boxes[0], periodic=(True, True, True), ncell=(50, 50, 3))
+    assert _ws([per], dims=2)[0] == kmc.KMC_EINVAL

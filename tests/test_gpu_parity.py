@@ -42,6 +42,8 @@ def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
     cfg["precision"] = _prec(kmc, precision)
     if w.dt_rule:
         cfg.update(dt_rule=w.dt_rule, dt_factor=w.dt_factor)
+    if w.dims == 2:
+        cfg.update(dims=2)
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics, **cfg)
     ref = O.Run(w)
     digests = []
@@ -67,6 +69,7 @@ def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
     print(f"[parity] ok exact={exact} rechecks={stats['rechecks']} fallbacks={stats['fallbacks']}", flush=True)
     sim.close()
     run_parity.last_stats = stats
+    run_parity.last_state = st
     return digests, exact
 
 
@@ -256,3 +259,25 @@ def test_autotune_launch_and_cells(kmc):
     assert boxes[0] == kmc.box_with_kappa(w.boxes[0], best["kappa"])
     w.boxes = boxes
     run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
+
+
+def test_autotune_cache_reuses_the_choice(kmc, tmp_path):
+    w = I.c1_small(steps=1)
+    cache = str(tmp_path / "tune.json")
+    b1, c1, t1 = kmc.autotune(w.boxes, w.state, device="cuda:0", steps=1, cache=cache, seed=w.seed)
+    b2, c2, t2 = kmc.autotune(w.boxes, w.state, device="cuda:0", steps=1, cache=cache, seed=w.seed)
+    assert not t1["cached"] and t2["cached"]
+    assert (b1, c1["search_mode"], c1["block_size"]) == (b2, c2["search_mode"], c2["block_size"])
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_planar_mode(kmc, precision, mode):
+    """Two-dimensional runs (one cell layer along z, planar scatter)."""
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    w = I.c1_planar(steps=6)
+    run_parity(kmc, w, 6, precision=precision, search_mode=sm)
+    st = run_parity.last_state
+    assert np.all(st[2] == 0.5) and np.all(st[5] == 0.0)
+    w = _adaptive(I.c1_planar(n=50_000, D=0.004, steps=3), 0.5, 10.0)
+    run_parity(kmc, w, 3, precision=precision, search_mode=sm, use_graph=True)

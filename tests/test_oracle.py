@@ -548,3 +548,85 @@ def test_adaptive_dt_run_accumulates_time_per_box():
             assert r.dt_last[b] == dt and dt <= box.dt
             tot[b] += dt
     assert r.time == tot
+
+
+# --------------------------------------------------------------------------
+# Planar mode (Section 1 also runs the method in two dimensions)
+# --------------------------------------------------------------------------
+
+def test_planar_directions_uniform_on_the_circle():
+    n = 100_000
+    d = np.array([O.direction(1, s, a, dims=2) for s in range(4) for a in range(n // 4)])
+    assert np.all(d[:, 2] == 0.0)
+    norm = np.sqrt(d[:, 0] ** 2 + d[:, 1] ** 2)
+    assert np.all(np.abs(norm - 1.0) < 8e-16)
+    # uniform angle: <cos> = <sin> = 0 (var 1/2), <cos^2> = 1/2 and
+    # <cos sin> = 0 (var 1/8)
+    assert np.all(np.abs(d[:, :2].mean(axis=0)) < 4 * math.sqrt(0.5 / n))
+    assert abs((d[:, 0] ** 2).mean() - 0.5) < 4 * math.sqrt(0.125 / n)
+    assert abs((d[:, 0] * d[:, 1]).mean()) < 4 * math.sqrt(0.125 / n)
+
+
+def test_planar_direction_is_the_doubled_polar_angle():
+    """The rational map equals (cos 2 phi, sin 2 phi) of the first accepted
+    disk point of the pair's random numbers, taken here from numpy's Philox
+    and trigonometry."""
+    seed, step = 77, 5
+    for a in (0, 1, 12345, 2**31 - 5):
+        found = None
+        for blk in range(32):
+            w = O.philox([blk, a, step, 0], [seed, 0])
+            for t in range(2):
+                e1 = 2.0 * ((w[2 * t] >> 11) * 2.0 ** -53) - 1.0
+                e2 = 2.0 * ((w[2 * t + 1] >> 11) * 2.0 ** -53) - 1.0
+                if 0.0 < e1 * e1 + e2 * e2 < 1.0:
+                    found = (e1, e2)
+                    break
+            if found:
+                break
+        phi = math.atan2(found[1], found[0])
+        n = O.direction(seed, step, a, dims=2)
+        assert abs(n[0] - math.cos(2 * phi)) < 4e-16 and abs(n[1] - math.sin(2 * phi)) < 4e-16
+        assert n[2] == 0.0
+
+
+def test_planar_collisions_conserve_and_stay_in_plane():
+    w = I.c1_planar(steps=3)
+    s0 = w.state.copy()
+    r = O.Run(w)
+    for _ in range(3):
+        npairs, _ = r.step()
+        assert npairs > 100
+    st = r.full_state()
+    assert np.all(st[2] == 0.5) and np.all(st[5] == 0.0)
+    p0, p1 = s0[3:5].sum(axis=1), st[3:5].sum(axis=1)
+    assert np.all(np.abs(p1 - p0) < 1e-10)
+    e0, e1 = (s0[3:5] ** 2).sum(), (st[3:5] ** 2).sum()
+    assert abs(e1 / e0 - 1.0) < 1e-12
+
+
+def test_planar_collision_rate_matches_kinetic_theory():
+    """First-step candidate pairs in a 2-D Maxwellian gas: (N(N-1)/2A) (2D)
+    <g> dt, the width 2D swept at the relative speed, with <g> = sigma_v
+    sqrt(pi) (|g| is Rayleigh with scale sqrt(2) sigma_v)."""
+    N = 100_000
+    D = (1.0 / N) ** 0.5
+    nc = int(math.floor(1.0 / (1.1 * D)))
+    gmean = math.sqrt(math.pi)
+    p = 0.005
+    dt = p / (N * 2.0 * D * gmean)
+    expect_per_seed = 0.5 * N * (N - 1) * 2.0 * D * gmean * dt
+    seeds = 160
+    got = 0
+    for sd in range(seeds):
+        rng = np.random.default_rng(20_000 + sd)
+        s = np.zeros((6, N))
+        s[0:2] = rng.random((2, N))
+        s[2] = 0.5
+        s[3:5] = rng.standard_normal((2, N))
+        box = I.Box(n=N, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(nc, nc, 1),
+                    periodic=(True, True, False), D2=D * D, dt=dt)
+        acc, _ = O.count_accepted(box, s)
+        got += acc // 2
+    expect = expect_per_seed * seeds
+    assert abs(got / expect - 1.0) < 0.02, (got, expect)
