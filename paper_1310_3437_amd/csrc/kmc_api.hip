@@ -144,8 +144,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.slot = (uint32_t*)take(4 * N);
     p.partner = (int32_t*)take(4 * N);
     p.sl_cnt = (uint32_t*)take(4 * N);
-    p.sl_idx = (uint32_t*)take(4 * N * kSlots);
-    p.sl_key = (double*)take(8 * N * kSlots);
+    p.sl = (SlotEntry*)take(sizeof(SlotEntry) * N * kSlots);
     p.fb_key = (double*)take(8 * N);
     p.fb_j = (int32_t*)take(4 * N);
     p.boxidx = nboxes > 1 ? (uint32_t*)take(4 * N) : nullptr;

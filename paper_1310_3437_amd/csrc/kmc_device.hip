@@ -619,8 +619,11 @@ __device__ __forceinline__ void post_candidate(const Plan& p, uint32_t i, uint32
 {
     const uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
     if (k < (uint32_t)kSlots) {
-        p.sl_idx[(size_t)k * p.N + i] = j;
-        p.sl_key[(size_t)k * p.N + i] = key;
+        SlotEntry e;
+        e.key = key;
+        e.j = j;
+        e.pad_ = 0u;
+        p.sl[(size_t)k * p.N + i] = e;
     }
 }
 
@@ -673,29 +676,38 @@ struct Found {
     // shift is the one the search used (that of the two cells).  All lanes
     // take the same branch-free path: loads first, then the arithmetic,
     // then the posts.  Returns the number of pairs examined (statistics).
-    template <int BATCH>
+    // BATCH records are loaded at a time; SKIP: no loads for empty slots
+    // (otherwise branch-free, loading the own record for them) -- measured
+    // per precision
+    template <int BATCH, bool SKIP>
     __device__ __forceinline__ uint32_t flush(const Plan& p, uint32_t i, const P64& me, const BoxDev& B)
     {
         double key[kReg];
         bool acc[kReg];
-        // BATCH records in flight at a time (register budget of the search)
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) {
+            acc[k] = false;
+            key[k] = __builtin_inf();
+        }
 #pragma unroll
         for (int h = 0; h < kReg; h += BATCH) {
-            P64 q[BATCH];
+            if (!SKIP || h < n) {
+                P64 q[BATCH];
 #pragma unroll
-            for (int e = 0; e < BATCH; ++e) q[e] = p.B[h + e < n ? j[h + e] : i];
+                for (int e = 0; e < BATCH; ++e) q[e] = p.B[h + e < n ? j[h + e] : (SKIP ? j[h] : i)];
 #pragma unroll
-            for (int e = 0; e < BATCH; ++e) {
-                const int k = h + e;
-                const uint32_t c = w >> (6 * k);
-                const int wx = (int)(c & 3u) - 1, wy = (int)((c >> 2) & 3u) - 1, wz = (int)((c >> 4) & 3u) - 1;
-                double rx = q[e].x - me.x, ry = q[e].y - me.y, rz = q[e].z - me.z;
-                if (wx != 0) rx = rx + (double)wx * B.L[0];
-                if (wy != 0) ry = ry + (double)wy * B.L[1];
-                if (wz != 0) rz = rz + (double)wz * B.L[2];
-                const PairQ pq = pair_q(rx, ry, rz, q[e].vx - me.vx, q[e].vy - me.vy, q[e].vz - me.vz);
-                acc[k] = k < n && accept(pq, B.D2, B.dt);
-                key[k] = acc[k] ? pq.c2 / pq.g2 : __builtin_inf();
+                for (int e = 0; e < BATCH; ++e) {
+                    const int k = h + e;
+                    const uint32_t c = w >> (6 * k);
+                    const int wx = (int)(c & 3u) - 1, wy = (int)((c >> 2) & 3u) - 1, wz = (int)((c >> 4) & 3u) - 1;
+                    double rx = q[e].x - me.x, ry = q[e].y - me.y, rz = q[e].z - me.z;
+                    if (wx != 0) rx = rx + (double)wx * B.L[0];
+                    if (wy != 0) ry = ry + (double)wy * B.L[1];
+                    if (wz != 0) rz = rz + (double)wz * B.L[2];
+                    const PairQ pq = pair_q(rx, ry, rz, q[e].vx - me.vx, q[e].vy - me.vy, q[e].vz - me.vz);
+                    acc[k] = k < n && accept(pq, B.D2, B.dt);
+                    key[k] = acc[k] ? pq.c2 / pq.g2 : __builtin_inf();
+                }
             }
         }
         double best_key = __builtin_inf();
@@ -714,8 +726,11 @@ struct Found {
 #pragma unroll
         for (int k = 0; k < kReg; ++k) {
             if (slot[k] < (uint32_t)kSlots) {
-                p.sl_idx[(size_t)slot[k] * p.N + j[k]] = i;
-                p.sl_key[(size_t)slot[k] * p.N + j[k]] = key[k];
+                SlotEntry e;
+                e.key = key[k];
+                e.j = i;
+                e.pad_ = 0u;
+                p.sl[(size_t)slot[k] * p.N + j[k]] = e;
             }
         }
         p.fb_key[i] = best_key;
@@ -750,6 +765,7 @@ struct PolF64 {
     static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
     static constexpr bool kScreen = false;
     static constexpr int kFlushBatch = 2;
+    static constexpr bool kFlushSkipEmpty = true;
     static constexpr int kWaves = 6;      // waves per SIMD the half search is compiled for
     struct Lds {
         P64 rec[W];
@@ -901,6 +917,7 @@ struct PolF32 {
     static constexpr int W = 160;         // staged records per chunk (5 KiB)
     static constexpr bool kScreen = true;
     static constexpr int kFlushBatch = 1;
+    static constexpr bool kFlushSkipEmpty = false;
     static constexpr int kWaves = 6;
     struct Lds {
         Rec32 r[W];
@@ -919,8 +936,8 @@ struct PolF32 {
     // Centre and thresholds of the group whose cells are x in [cxf, cxl] of
     // row (gcy, gcz); its neighbourhood spans cells cxf-1..cxl+1, gcy-1..gcy+1,
     // gcz-1..gcz+1 (images included).
-    __device__ static void begin_group(const Plan& p, const BoxDev& B, Own& o, Group& g, int cxf, int cxl,
-                                       int gcy, int gcz, int gb, uint32_t i, bool in)
+    __device__ static void group_ctx(const Plan& p, const BoxDev& B, Group& g, int cxf, int cxl, int gcy, int gcz,
+                                     int gb)
     {
         const int clo[3] = {cxf - 1, gcy - 1, gcz - 1}, chi[3] = {cxl + 1, gcy + 1, gcz + 1};
 #pragma unroll
@@ -929,6 +946,11 @@ struct PolF32 {
             g.X0[k] = B.lo[k] + 0.5 * (double)(clo[k] + chi[k] + 1) * h;
         }
         g.t = p.box_sb[gb];
+    }
+    __device__ static void begin_group(const Plan& p, const BoxDev& B, Own& o, Group& g, int cxf, int cxl,
+                                       int gcy, int gcz, int gb, uint32_t i, bool in)
+    {
+        group_ctx(p, B, g, cxf, cxl, gcy, gcz, gb);
         if (in) {
             const P64 m = p.B[i];
             o.x = (float)(m.x - g.X0[0]);
@@ -1101,7 +1123,9 @@ void k_search_half(Plan p)
             }
         }
     }
-    uint64_t c = valid ? found.template flush<Pol::kFlushBatch>(p, i, Pol::self64(p, i, own), p.boxes[bidx]) : 0u;
+    uint64_t c = valid ? found.template flush<Pol::kFlushBatch, Pol::kFlushSkipEmpty>(p, i, Pol::self64(p, i, own),
+                                                                                       p.boxes[bidx])
+                       : 0u;
     // statistics: pairs the search kept, counted at both particles
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
@@ -1257,8 +1281,9 @@ __global__ __launch_bounds__(256) void k_finish(Plan p)
     int32_t best = valid ? p.fb_j[i] : -1;
     if (cnt >= 1 && cnt <= (uint32_t)kSlots) {
         for (uint32_t k = 0; k < cnt; ++k) {
-            const uint32_t j = p.sl_idx[(size_t)k * p.N + i];
-            const double key = p.sl_key[(size_t)k * p.N + i];
+            const SlotEntry e = p.sl[(size_t)k * p.N + i];
+            const uint32_t j = e.j;
+            const double key = e.key;
             if (best < 0 || key < best_key ||
                 (key == best_key && p.idB[j] < p.idB[best])) {
                 best_key = key;

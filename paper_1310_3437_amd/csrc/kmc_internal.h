@@ -48,6 +48,13 @@ struct alignas(16) P64 {
     double x, y, z, vx, vy, vz;
 };
 
+// Candidate list entry: one 16-byte store per posted pair.
+struct alignas(16) SlotEntry {
+    double key;      // c2 / g2 of the pair (the same from both sides)
+    uint32_t j;      // sorted index of the other particle
+    uint32_t pad_;
+};
+
 // Per-context control block in device memory.
 struct Ctl {
     unsigned long long step;            // global index of the next step
@@ -88,8 +95,7 @@ struct Plan {
     uint32_t* slot;                // per particle in A order: rank inside its cell
     int32_t* partner;              // per sorted particle: sorted index of partner or -1
     uint32_t* sl_cnt;              // per sorted particle: entries posted to its candidate list
-    uint32_t* sl_idx;              // [kSlots][N]: sorted index of the other particle
-    double* sl_key;                // [kSlots][N]: FP64 key of that pair
+    SlotEntry* sl;                 // [kSlots][N]: (FP64 key, sorted index of the other particle)
     double* fb_key;                // per sorted particle: key of its forward best (inf: none)
     int32_t* fb_j;                 // per sorted particle: its forward best (-1: none)
     uint32_t* boxidx;              // per particle: its box (null when there is one box)
