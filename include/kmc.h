@@ -59,7 +59,7 @@ typedef enum {
 
 typedef enum { KMC_FP64 = 0, KMC_FP32_SCREEN = 1 } kmc_precision;
 typedef enum { KMC_GEOM_BOX = 0, KMC_GEOM_SPHERE = 1 } kmc_geometry;
-typedef enum { KMC_BC_REFLECT = 0, KMC_BC_PERIODIC = 1 } kmc_bc;
+typedef enum { KMC_BC_REFLECT = 0, KMC_BC_PERIODIC = 1, KMC_BC_ABSORB = 2 } kmc_bc;
 typedef enum { KMC_KIN_AT_TSTAR = 0, KMC_KIN_VEL_ONLY = 1 } kmc_kinematics;
 typedef enum { KMC_DT_FIXED = 0, KMC_DT_ADAPTIVE = 1 } kmc_dt_rule;
 /* How the partner search is organised (the result is the same):
@@ -78,7 +78,13 @@ typedef enum { KMC_SEARCH_HALF = 0, KMC_SEARCH_FULL = 1 } kmc_search_mode;
  *   geometry  KMC_GEOM_BOX: faces at lo/hi with per-axis bc;
  *             KMC_GEOM_SPHERE: reflecting sphere of radius sphere_r about the
  *             origin inside the cell grid lo..hi (bc must be REFLECT);
- *   bc[k]     KMC_BC_PERIODIC or KMC_BC_REFLECT for axis k;
+ *   bc[k]     KMC_BC_PERIODIC, KMC_BC_REFLECT or KMC_BC_ABSORB for axis k
+ *             (Section 1 names reflective, absorptive and periodic boxes).
+ *             Absorbing faces (geometry BOX only): a particle whose streamed
+ *             position lies beyond them (x < lo or x > hi on that axis) at
+ *             the end of a step leaves the gas for good: it is in no cell,
+ *             never searches, collides or moves again, its partner is -1,
+ *             and kmc_read_state reports the state it had when it left;
  *   ncell[k]  cells (bins) along axis k; >= 1, and >= 3 on periodic axes;
  *   lo, hi    grid (and box) bounds, hi > lo;
  *   inv_h[k]  ncell[k] / (hi[k] - lo[k]) as computed by the caller (the
@@ -178,6 +184,7 @@ typedef struct kmc_stats {
     uint64_t candidates;       /* pairs the search recorded per particle, summed over
                                   particles and steps (FP64: acceptable pairs; FP32
                                   screen: pairs it could not reject)                    */
+    uint64_t absorbed;         /* particles absorbed by absorbing faces so far          */
 } kmc_stats;
 
 typedef struct kmc_ctx kmc_ctx;

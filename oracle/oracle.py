@@ -25,6 +25,7 @@ class OrcBox(C.Structure):
         ("ncell", C.c_int32 * 3),
         ("kinematics", C.c_int32),
         ("dims", C.c_int32),
+        ("absorb", C.c_int32 * 3),
         ("lo", C.c_double * 3),
         ("hi", C.c_double * 3),
         ("inv_h", C.c_double * 3),
@@ -72,13 +73,17 @@ def lib():
         L.orc_pair_hash.argtypes = [C.c_uint32, C.c_uint32]
         L.orc_pair_hash.restype = C.c_uint64
         L.orc_step.argtypes = [bp, dp, u32p, C.c_uint64, i32p, u64p, u64p, C.c_int, u64p]
+        L.orc_step_ex.argtypes = [bp, dp, u32p, C.POINTER(C.c_uint8), C.c_uint64, i32p, u64p, u64p, C.c_int,
+                                  u64p]
+        L.orc_adaptive_dt_ex.argtypes = [bp, dp, C.POINTER(C.c_uint8), C.c_double, dp]
         L.orc_count_accepted.argtypes = [bp, dp, u32p, C.c_int, u64p, u64p]
         L.orc_adaptive_dt.argtypes = [bp, dp, C.c_double, dp]
         L.orc_step_sampled.argtypes = [bp, dp, u32p, C.c_uint64, C.POINTER(C.c_int64), C.c_int64, i32p,
                                        dp, C.c_int]
         L.orc_max_threads.argtypes = []
         for f in ("orc_cell_coords", "orc_pair", "orc_find_partners", "orc_find_partners_bruteforce",
-                  "orc_step", "orc_count_accepted", "orc_step_sampled", "orc_adaptive_dt",
+                  "orc_step", "orc_step_ex", "orc_count_accepted", "orc_step_sampled", "orc_adaptive_dt",
+                  "orc_adaptive_dt_ex",
                   "orc_max_threads"):
             getattr(L, f).restype = C.c_int
         _LIB = L
@@ -97,6 +102,7 @@ def make_box(box, seed=1, kinematics=0, dims=3):
     ob.sphere = 1 if box.sphere else 0
     for k in range(3):
         ob.periodic[k] = 1 if box.periodic[k] else 0
+        ob.absorb[k] = 1 if getattr(box, "absorb", (False,) * 3)[k] else 0
         ob.ncell[k] = int(box.ncell[k])
         ob.lo[k] = float(box.lo[k])
         ob.hi[k] = float(box.hi[k])
@@ -192,13 +198,15 @@ def pair_hash(a, b):
     return int(lib().orc_pair_hash(int(a), int(b)))
 
 
-def adaptive_dt(box, state, factor=1.0):
-    """The adaptive time step of one box for the given state."""
+def adaptive_dt(box, state, factor=1.0, gone=None):
+    """The adaptive time step of one box for the given state (particles with
+    gone[i] != 0 excluded)."""
     s = _soa(state)
     ob = make_box(box)
     ob.n = s.shape[1]
     out = C.c_double(0.0)
-    rc = lib().orc_adaptive_dt(C.byref(ob), _ptr(s, C.c_double), float(factor), C.byref(out))
+    g = None if gone is None else _ptr(np.ascontiguousarray(gone, dtype=np.uint8), C.c_uint8)
+    rc = lib().orc_adaptive_dt_ex(C.byref(ob), _ptr(s, C.c_double), g, float(factor), C.byref(out))
     if rc != 0:
         raise ValueError(f"orc_adaptive_dt failed ({rc})")
     return float(out.value)
@@ -224,9 +232,11 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, d
     return partner, out.T.copy()
 
 
-def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3):
+def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, gone=None):
     """One oracle step of one box, in place on `state` ((6, n) float64,
-    C-contiguous).  Returns (partner indices, npairs, digest, pair_tests)."""
+    C-contiguous) and on `gone` (uint8 per particle, 1 = absorbed; required
+    with absorbing faces).  Returns (partner indices, npairs, digest,
+    pair_tests)."""
     assert state.dtype == np.float64 and state.flags.c_contiguous and state.shape[0] == 6
     n = state.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
@@ -236,9 +246,12 @@ def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3):
     npairs = C.c_uint64(0)
     dig = C.c_uint64(0)
     tests = C.c_uint64(0)
-    rc = lib().orc_step(C.byref(ob), _ptr(state, C.c_double), _ptr(ids, C.c_uint32), int(step),
-                        _ptr(partner, C.c_int32), C.byref(npairs), C.byref(dig), int(nthreads),
-                        C.byref(tests))
+    if gone is not None:
+        assert gone.dtype == np.uint8 and gone.flags.c_contiguous and gone.shape == (n,)
+    rc = lib().orc_step_ex(C.byref(ob), _ptr(state, C.c_double), _ptr(ids, C.c_uint32),
+                           None if gone is None else _ptr(gone, C.c_uint8), int(step),
+                           _ptr(partner, C.c_int32), C.byref(npairs), C.byref(dig), int(nthreads),
+                           C.byref(tests))
     if rc != 0:
         raise ValueError(f"orc_step failed ({rc})")
     return partner, int(npairs.value), int(dig.value), int(tests.value)
@@ -262,6 +275,7 @@ class Run:
         self.nthreads = nthreads
         self.partner_by_id = None
         self.pair_tests = 0
+        self.gone = [np.zeros(self.off[b + 1] - self.off[b], dtype=np.uint8) for b in range(len(workload.boxes))]
         self.time = [0.0] * len(workload.boxes)
         self.dt_last = [float(b.dt) for b in workload.boxes]
 
@@ -272,12 +286,12 @@ class Run:
         pb = np.full(self.off[-1], -1, dtype=np.int64)
         for b, box in enumerate(self.w.boxes):
             if getattr(self.w, "dt_rule", 0) == 1:
-                box = dataclasses.replace(box, dt=adaptive_dt(box, self.state[b], self.w.dt_factor))
+                box = dataclasses.replace(box, dt=adaptive_dt(box, self.state[b], self.w.dt_factor, self.gone[b]))
             self.dt_last[b] = float(box.dt)
             self.time[b] += float(box.dt)
             p, npairs, dig, t = step_box(box, self.state[b], self.ids[b], self.step_index,
                                          seed=self.w.seed, kinematics=self.w.kinematics,
-                                         dims=getattr(self.w, "dims", 3),
+                                         dims=getattr(self.w, "dims", 3), gone=self.gone[b],
                                          nthreads=self.nthreads)
             ids = self.ids[b]
             has = p >= 0
@@ -289,6 +303,10 @@ class Run:
         self.pair_tests = tests
         self.step_index += 1
         return tot_pairs, tot_dig
+
+    def absorbed(self):
+        """Particles absorbed so far (all boxes)."""
+        return int(sum(int(g.sum()) for g in self.gone))
 
     def full_state(self):
         """(6, N) state in id order."""

@@ -39,6 +39,8 @@ static int box_ok(const orc_box* b)
     if (b->sphere && !(b->R > 0.0)) return 0;
     if (b->dims != 0 && b->dims != 2 && b->dims != 3) return 0;
     if (b->dims == 2 && (b->ncell[2] != 1 || b->periodic[2] || b->sphere)) return 0;
+    for (int k = 0; k < 3; ++k)
+        if (b->absorb[k] && (b->periodic[k] || b->sphere)) return 0;
     return 1;
 }
 
@@ -131,7 +133,7 @@ typedef struct {
     int64_t* member;  /* n: particle indices grouped by bin, index order within a bin */
 } csr_t;
 
-static int build_csr(const orc_box* b, const double* s, csr_t* t)
+static int build_csr(const orc_box* b, const double* s, const unsigned char* gone, csr_t* t)
 {
     int64_t n = b->n;
     t->ncells = (int64_t)b->ncell[0] * b->ncell[1] * b->ncell[2];
@@ -143,6 +145,7 @@ static int build_csr(const orc_box* b, const double* s, csr_t* t)
         return -1;
     }
     for (int64_t i = 0; i < n; ++i) {
+        if (gone && gone[i]) { cellof[i] = -1; continue; }   /* in no bin */
         int32_t c[3];
         orc_cell_coords(b, s[i], s[n + i], s[2 * n + i], c);
         cellof[i] = linear_cell(b, c);
@@ -155,7 +158,8 @@ static int build_csr(const orc_box* b, const double* s, csr_t* t)
         return -1;
     }
     memcpy(fill, t->start, (size_t)t->ncells * sizeof(int64_t));
-    for (int64_t i = 0; i < n; ++i) t->member[fill[cellof[i]]++] = i;
+    for (int64_t i = 0; i < n; ++i)
+        if (cellof[i] >= 0) t->member[fill[cellof[i]]++] = i;
     free(fill);
     free(cellof);
     return 0;
@@ -227,8 +231,8 @@ static int64_t search_one(const orc_box* b, const double* s, const uint32_t* ids
 }
 
 static int64_t search_with_csr(const orc_box* b, const double* s, const uint32_t* ids,
-                               const csr_t* t, int32_t* partner, int nthreads,
-                               uint64_t* pair_tests, uint64_t* accepted)
+                               const unsigned char* gone, const csr_t* t, int32_t* partner,
+                               int nthreads, uint64_t* pair_tests, uint64_t* accepted)
 {
     int64_t n = b->n;
     uint64_t tests = 0, acc_count = 0;
@@ -240,6 +244,7 @@ static int64_t search_with_csr(const orc_box* b, const double* s, const uint32_t
 #endif
     for (int64_t i = 0; i < n; ++i) {
         uint64_t nt_i = 0, na_i = 0;
+        if (gone && gone[i]) { partner[i] = -1; continue; }
         partner[i] = (int32_t)search_one(b, s, ids, t, i, &nt_i, &na_i);
         tests += nt_i;
         acc_count += na_i;
@@ -255,8 +260,8 @@ int orc_find_partners(const orc_box* b, const double* s, const uint32_t* ids,
     if (!box_ok(b) || (b->n > 0 && (!s || !ids || !partner))) return -1;
     if (b->n > INT32_MAX) return -1;
     csr_t t;
-    if (build_csr(b, s, &t) != 0) return -2;
-    search_with_csr(b, s, ids, &t, partner, nthreads, pair_tests, NULL);
+    if (build_csr(b, s, NULL, &t) != 0) return -2;
+    search_with_csr(b, s, ids, NULL, &t, partner, nthreads, pair_tests, NULL);
     free_csr(&t);
     return 0;
 }
@@ -269,8 +274,8 @@ int orc_count_accepted(const orc_box* b, const double* s, const uint32_t* ids,
     int32_t* partner = (int32_t*)malloc((size_t)(b->n > 0 ? b->n : 1) * sizeof(int32_t));
     if (!partner) return -2;
     csr_t t;
-    if (build_csr(b, s, &t) != 0) { free(partner); return -2; }
-    search_with_csr(b, s, ids, &t, partner, nthreads, pair_tests, accepted);
+    if (build_csr(b, s, NULL, &t) != 0) { free(partner); return -2; }
+    search_with_csr(b, s, ids, NULL, &t, partner, nthreads, pair_tests, accepted);
     free_csr(&t);
     free(partner);
     return 0;
@@ -449,6 +454,7 @@ static void apply_bc(const orc_box* b, double x[3], double v[3])
     }
     for (int k = 0; k < 3; ++k) {
         double lo = b->lo[k], hi = b->hi[k];
+        if (b->absorb[k]) continue;   /* decided after streaming */
         if (b->periodic[k]) {
             double L = hi - lo;
             if (x[k] >= hi) x[k] = x[k] - L;
@@ -469,6 +475,12 @@ static void apply_bc(const orc_box* b, double x[3], double v[3])
 
 int orc_adaptive_dt(const orc_box* b, const double* s, double factor, double* dt)
 {
+    return orc_adaptive_dt_ex(b, s, NULL, factor, dt);
+}
+
+int orc_adaptive_dt_ex(const orc_box* b, const double* s, const unsigned char* gone, double factor,
+                       double* dt)
+{
     if (!box_ok(b) || !dt || (b->n > 0 && !s) || !(factor > 0.0)) return -1;
     int64_t n = b->n;
     double dx = (b->hi[0] - b->lo[0]) / b->ncell[0];
@@ -478,6 +490,7 @@ int orc_adaptive_dt(const orc_box* b, const double* s, double factor, double* dt
     }
     double v2max = 0.0;
     for (int64_t i = 0; i < n; ++i) {
+        if (gone && gone[i]) continue;
         double vx = s[3 * n + i], vy = s[4 * n + i], vz = s[5 * n + i];
         double v2 = fma(vz, vz, fma(vy, vy, vx * vx));
         if (v2 > v2max) v2max = v2;
@@ -552,8 +565,24 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
              int32_t* partner_out, uint64_t* npairs, uint64_t* digest,
              int nthreads, uint64_t* pair_tests)
 {
+    return orc_step_ex(b, s, ids, NULL, step, partner_out, npairs, digest, nthreads, pair_tests);
+}
+
+/* A particle beyond an absorbing face after streaming leaves the gas. */
+static int absorbed(const orc_box* b, const double x[3])
+{
+    for (int k = 0; k < 3; ++k)
+        if (b->absorb[k] && (x[k] < b->lo[k] || x[k] > b->hi[k])) return 1;
+    return 0;
+}
+
+int orc_step_ex(const orc_box* b, double* s, const uint32_t* ids, unsigned char* gone, uint64_t step,
+                int32_t* partner_out, uint64_t* npairs, uint64_t* digest,
+                int nthreads, uint64_t* pair_tests)
+{
     if (!box_ok(b) || (b->n > 0 && (!s || !ids))) return -1;
     if (b->n > INT32_MAX) return -1;
+    if (!gone && (b->absorb[0] || b->absorb[1] || b->absorb[2])) return -1;
     int64_t n = b->n;
     size_t nn = (size_t)(n > 0 ? n : 1);
     int32_t* partner = partner_out ? partner_out : (int32_t*)malloc(nn * sizeof(int32_t));
@@ -568,12 +597,12 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
 
     /* 1-2: bins and partner search */
     csr_t t;
-    if (build_csr(b, s, &t) != 0) {
+    if (build_csr(b, s, gone, &t) != 0) {
         if (!partner_out) free(partner);
         free(nv); free(ts); free(hit);
         return -2;
     }
-    search_with_csr(b, s, ids, &t, partner, nthreads, pair_tests, NULL);
+    search_with_csr(b, s, ids, gone, &t, partner, nthreads, pair_tests, NULL);
     free_csr(&t);
 
     /* 3: a pair collides only if each particle chose the other.  The pair is
@@ -597,8 +626,10 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
         dig += orc_pair_hash(ids[a], ids[c]);
     }
 
-    /* 4: free streaming and boundary conditions */
+    /* 4: free streaming and boundary conditions; particles that have left
+     * the gas stay where they are */
     for (int64_t i = 0; i < n; ++i) {
+        if (gone && gone[i]) continue;
         double x[3], v[3], vn[3];
         for (int k = 0; k < 3; ++k) {
             x[k] = s[(size_t)k * nn + (size_t)i];
@@ -606,6 +637,7 @@ int orc_step(const orc_box* b, double* s, const uint32_t* ids, uint64_t step,
             vn[k] = nv[(size_t)k * nn + (size_t)i];
         }
         advance_one(b, x, v, hit[i], vn, ts[i]);
+        if (gone && absorbed(b, x)) gone[i] = 1;
         for (int k = 0; k < 3; ++k) {
             s[(size_t)k * nn + (size_t)i] = x[k];
             s[(size_t)(3 + k) * nn + (size_t)i] = v[k];
@@ -638,7 +670,7 @@ int orc_step_sampled(const orc_box* b, const double* s, const uint32_t* ids, uin
         if (sel[k] < 0 || sel[k] >= b->n) return -1;
     int64_t n = b->n;
     csr_t t;
-    if (build_csr(b, s, &t) != 0) return -2;
+    if (build_csr(b, s, NULL, &t) != 0) return -2;
 #ifdef _OPENMP
     int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nt)

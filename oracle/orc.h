@@ -50,6 +50,9 @@ typedef struct {
     int32_t  dims;         /* 3 (or 0): space; 2: planar mode (one bin along z,
                               no periodic z, no sphere; isotropic scatter in the
                               x-y plane; z and vz stay as given)              */
+    int32_t  absorb[3];    /* per axis: 1 absorbing faces lo/hi (not periodic,
+                              no sphere): a particle whose streamed position
+                              lies beyond them leaves the gas for good       */
     double   lo[3], hi[3]; /* box (and bin grid) bounds                         */
     double   inv_h[3];     /* ncell[k] / (hi[k] - lo[k]), supplied by the caller */
     double   R;            /* sphere radius (sphere == 1)                       */
@@ -97,6 +100,15 @@ void orc_direction2(uint64_t seed, uint64_t step, uint32_t a, double n[3]);
 /* 64-bit hash of an unordered pair (a < b), used for the per-step digest. */
 uint64_t orc_pair_hash(uint32_t a, uint32_t b);
 
+/* One full step with absorbing faces: gone[i] != 0 marks a particle that
+ * has left the gas (it is in no bin, never searches or collides, and its
+ * state stays as it was); particles absorbed during this step get gone[i] = 1.
+ * gone may be NULL (no particle has left and none is absorbed).  Otherwise as
+ * orc_step. */
+int orc_step_ex(const orc_box* b, double* s, const uint32_t* ids, unsigned char* gone, uint64_t step,
+                int32_t* partner, uint64_t* npairs, uint64_t* digest,
+                int nthreads, uint64_t* pair_tests);
+
 /* One full step in place: search, mutual resolve, scatter, free-stream,
  * boundary conditions.  partner (optional, n entries) receives the search
  * result (array indices); npairs/digest receive the collision count and the
@@ -119,6 +131,11 @@ int orc_step_sampled(const orc_box* b, const double* s, const uint32_t* ids, uin
  * speed in s, *dt = min(b->dt, factor * dx / v_max), or b->dt when every
  * particle is at rest. */
 int orc_adaptive_dt(const orc_box* b, const double* s, double factor, double* dt);
+
+/* The same over the particles still in the gas (gone[i] == 0; gone may be
+ * NULL). */
+int orc_adaptive_dt_ex(const orc_box* b, const double* s, const unsigned char* gone, double factor,
+                       double* dt);
 
 /* Ordered pairs (i, j != i) examined and ordered pairs accepted by the
  * partner criteria in the current state, without choosing partners; used by

@@ -46,7 +46,8 @@ int check_box(const kmc_box& b)
     if (!finite_pos(b.D2) || !finite_pos(b.dt)) return KMC_EINVAL;
     const double D = std::sqrt(b.D2);
     for (int k = 0; k < 3; ++k) {
-        if (b.bc[k] != KMC_BC_REFLECT && b.bc[k] != KMC_BC_PERIODIC) return KMC_EINVAL;
+        if (b.bc[k] != KMC_BC_REFLECT && b.bc[k] != KMC_BC_PERIODIC && b.bc[k] != KMC_BC_ABSORB) return KMC_EINVAL;
+        if (b.bc[k] == KMC_BC_ABSORB && b.geometry != KMC_GEOM_BOX) return KMC_EINVAL;
         if (b.ncell[k] < 1) return KMC_EINVAL;
         if (b.bc[k] == KMC_BC_PERIODIC && b.ncell[k] < 3) return KMC_EINVAL;
         if (!std::isfinite(b.lo[k]) || !std::isfinite(b.hi[k]) || !(b.hi[k] > b.lo[k])) return KMC_EINVAL;
@@ -87,7 +88,7 @@ int totals(const kmc_box* boxes, uint32_t nboxes, Totals& t)
 {
     for (uint32_t b = 0; b < nboxes; ++b) {
         t.N += boxes[b].n;
-        t.C += (uint64_t)boxes[b].ncell[0] * (uint64_t)boxes[b].ncell[1] * (uint64_t)boxes[b].ncell[2];
+        t.C += (uint64_t)boxes[b].ncell[0] * (uint64_t)boxes[b].ncell[1] * (uint64_t)boxes[b].ncell[2] + 1u;
     }
     if (t.N > 0x7FFFFFFFull) return KMC_EOVERFLOW;
     if (t.C > 0xFFFFFFFEull) return KMC_EOVERFLOW;
@@ -184,6 +185,7 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
         d.inv_h[k] = b.inv_h[k];
         d.nc[k] = b.ncell[k];
         d.periodic[k] = b.bc[k] == KMC_BC_PERIODIC ? 1 : 0;
+        d.absorb[k] = b.bc[k] == KMC_BC_ABSORB ? 1 : 0;
         d.ctr32[k] = (float)(0.5 * (b.lo[k] + b.hi[k]));
         d.L32[k] = (float)d.L[k];
     }
@@ -291,7 +293,7 @@ int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const
     uint64_t coff = 0, poff = 0;
     for (uint32_t b = 0; b < nboxes; ++b) {
         fill_box_dev(bd[b], boxes[b], (uint32_t)coff, (uint32_t)poff);
-        coff += (uint64_t)boxes[b].ncell[0] * boxes[b].ncell[1] * boxes[b].ncell[2];
+        coff += (uint64_t)boxes[b].ncell[0] * boxes[b].ncell[1] * boxes[b].ncell[2] + 1u;   // + absorbed cell
         poff += boxes[b].n;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -443,6 +445,7 @@ int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
         uint64_t tot = 0;
         for (int l = 0; l < kHistLanes; ++l) tot += acc[l];
         out->candidates = tot;
+    out->absorbed = ctl.absorbed_total;
     }
     for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
     out->search_kernel_ms = c->search_kernel_ms;

@@ -232,7 +232,7 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
         p.ctl->fallbacks_total = 0;
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
-        p.ctl->work_next = 0;
+        p.ctl->absorbed_total = 0;
     }
     for (uint32_t k = t; k < (uint32_t)kHistLanes; k += blockDim.x) {
         p.hist_np[k] = 0;
@@ -246,8 +246,8 @@ __global__ void k_read_partners(Plan p, int32_t* __restrict__ out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.N) return;
-    const int32_t q = p.partner[i];
-    out[p.idB[i]] = q >= 0 ? (int32_t)p.idB[q] : -1;
+    const int32_t q = p.partner[i];   // an absorbed particle has none, nor is it anyone's
+    out[p.idB[i] & ~kGone] = q >= 0 ? (int32_t)p.idB[q] : -1;
 }
 
 __global__ void k_read_state(Plan p, double* __restrict__ out)
@@ -255,7 +255,7 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.N) return;
     const size_t N = p.N;
-    const uint32_t id = p.idA[i];
+    const uint32_t id = p.idA[i] & ~kGone;
 #pragma unroll
     for (int k = 0; k < 6; ++k) out[k * N + id] = p.A[k * N + i];
 }
@@ -270,14 +270,19 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
 // and each run of equal cells takes its slots with one atomic issued by the
 // run's first lane.  Every lane of the wave must call this.
 __device__ __forceinline__ void bin_particle(const Plan& p, uint32_t i, bool valid, const BoxDev& B, double x,
-                                             double y, double z)
+                                             double y, double z, bool gone)
 {
     uint32_t c = 0xFFFFFFFFu;
     if (valid) {
-        const int cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
-        const int cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
-        const int cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
-        c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+        if (gone) {
+            // the box's cell of absorbed particles, after its grid
+            c = B.coff + (uint32_t)B.nc[0] * (uint32_t)B.nc[1] * (uint32_t)B.nc[2];
+        } else {
+            const int cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
+            const int cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
+            const int cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
+            c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+        }
         p.cell[i] = c;
     }
     const int lane = threadIdx.x & 63;
@@ -304,7 +309,8 @@ __global__ void k_bin(Plan p)
     const bool valid = i < p.N;
     const size_t N = p.N;
     const BoxDev& B = box_of(p, valid ? i : 0u);
-    bin_particle(p, i, valid, B, valid ? p.A[i] : 0.0, valid ? p.A[N + i] : 0.0, valid ? p.A[2 * N + i] : 0.0);
+    bin_particle(p, i, valid, B, valid ? p.A[i] : 0.0, valid ? p.A[N + i] : 0.0, valid ? p.A[2 * N + i] : 0.0,
+                 false);
 }
 
 // --------------------------------------------------------------------------
@@ -367,7 +373,6 @@ __global__ __launch_bounds__(1024) void k_scan_partials(Plan p)
     if (threadIdx.x == 0) {
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
-        p.ctl->work_next = 0;
         p.ctl->ovf_count = 0;
     }
     for (uint32_t b = threadIdx.x; b < p.nboxes; b += blockDim.x) p.box_vmax[b] = 0u;
@@ -423,7 +428,9 @@ __global__ void k_scatter(Plan p)
         r.vy = vy = p.A[4 * N + i];
         r.vz = vz = p.A[5 * N + i];
         p.B[d] = r;
-        p.idB[d] = p.idA[i];
+        const uint32_t id = p.idA[i];
+        p.idB[d] = id;
+        if (id & kGone) vx = vy = vz = 0.0;   // not in the gas: no part in the adaptive step
         if (F32) vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
     }
     __shared__ float wmax[16];
@@ -565,6 +572,7 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
 // straight from the sorted records (rechecks, list overflow, fallback).
 __device__ int32_t search_one64(const Plan& p, uint32_t i)
 {
+    if (p.idB[i] & kGone) return -1;
     const BoxDev& B = box_of(p, i);
     const P64* __restrict__ X = p.B;
     const P64 me = X[i];
@@ -1038,10 +1046,11 @@ void k_search_half(Plan p)
     const int lane = threadIdx.x;
     const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * 64u + (uint32_t)lane;
     const bool valid = i < p.N;
+    const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
     typename Pol::Own own;
-    if (valid) {
+    if (alive) {
         bidx = p.boxidx ? p.boxidx[i] : 0u;
         const BoxDev& B = p.boxes[bidx];
         double x, y, z;
@@ -1056,11 +1065,11 @@ void k_search_half(Plan p)
     found.w = 0u;
 #pragma unroll
     for (int k = 0; k < kReg; ++k) found.j[k] = 0;
-    uint64_t remaining = __ballot(valid);
+    uint64_t remaining = __ballot(alive);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
-        const uint64_t grp = __ballot(valid && rowkey == key) & remaining;
+        const uint64_t grp = __ballot(alive && rowkey == key) & remaining;
         remaining &= ~grp;
         const bool in = (grp >> lane) & 1ull;
         const int last = 63 - __clzll((long long)grp);
@@ -1147,10 +1156,11 @@ void k_search_full(Plan p)
     const int lane = threadIdx.x;
     const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * 64u + (uint32_t)lane;
     const bool valid = i < p.N;
+    const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
     typename Pol::Own own;
-    if (valid) {
+    if (alive) {
         bidx = p.boxidx ? p.boxidx[i] : 0u;
         const BoxDev& B = p.boxes[bidx];
         double x, y, z;
@@ -1166,11 +1176,11 @@ void k_search_full(Plan p)
     best.j = -1;
     best.accepted = 0u;
     best.screened = 0u;
-    uint64_t remaining = __ballot(valid);
+    uint64_t remaining = __ballot(alive);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
-        const uint64_t grp = __ballot(valid && rowkey == key) & remaining;
+        const uint64_t grp = __ballot(alive && rowkey == key) & remaining;
         remaining &= ~grp;
         const bool in = (grp >> lane) & 1ull;
         const int last = 63 - __clzll((long long)grp);
@@ -1342,6 +1352,7 @@ __device__ __forceinline__ void apply_bc(const BoxDev& B, double x[3], double v[
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double lo = B.lo[k], hi = B.hi[k];
+        if (B.absorb[k]) continue;   // decided by the caller after streaming
         if (B.periodic[k]) {
             if (x[k] >= hi) x[k] = x[k] - B.L[k];
             else if (x[k] < lo) x[k] = x[k] + B.L[k];
@@ -1360,12 +1371,14 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t my_np = 0, my_dig = 0;
     double nx = 0.0, ny = 0.0, nz = 0.0;
+    bool gone = false, left = false;
     if (i < p.N) {
         const BoxDev& B = box_of(p, i);
         const size_t N = p.N;
         const P64 me = p.B[i];
         double x[3] = {me.x, me.y, me.z}, v[3] = {me.vx, me.vy, me.vz};
-        const uint32_t id = p.idB[i];
+        uint32_t id = p.idB[i];
+        gone = (id & kGone) != 0u;   // absorbed earlier: keeps its state
         const int32_t q = p.partner[i];
         const double dt = B.dt;
         bool hit = false;
@@ -1416,11 +1429,21 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
                 my_dig = pair_hash(ida, idb);
             }
         }
-        if (!hit) {
+        if (!hit && !gone) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) x[k] = x[k] + v[k] * dt;
         }
-        apply_bc(B, x, v);
+        if (!gone) {
+            apply_bc(B, x, v);
+            // absorbing faces: beyond them the particle leaves the gas
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (B.absorb[k] && (x[k] < B.lo[k] || x[k] > B.hi[k])) left = true;
+            if (left) {
+                id |= kGone;
+                gone = true;
+            }
+        }
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             p.A[k * N + i] = x[k];
@@ -1430,7 +1453,9 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
         nx = x[0]; ny = x[1]; nz = x[2];
     }
     // a1 of the next step: cell and slot of the new position
-    bin_particle(p, i, i < p.N, box_of(p, i < p.N ? i : 0u), nx, ny, nz);
+    bin_particle(p, i, i < p.N, box_of(p, i < p.N ? i : 0u), nx, ny, nz, gone);
+    const uint64_t lm = __ballot(left);
+    if ((threadIdx.x & 63) == 0 && lm) atomicAdd(&p.ctl->absorbed_total, (unsigned long long)__popcll(lm));
     block_sum2(my_np, my_dig, lds);
     if (threadIdx.x == 0 && my_np != 0) {
         const size_t row = (size_t)(p.ctl->steps_done % p.H) * kHistLanes + (blockIdx.x % kHistLanes);
@@ -1465,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_count_tests(Plan p, unsigned long long*
     __shared__ uint64_t lds[32];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t t = 0, z = 0;
-    if (i < p.N) {
+    if (i < p.N && !(p.idB[i] & kGone)) {
         const BoxDev& B = box_of(p, i);
         const P64 me = p.B[i];
         const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);

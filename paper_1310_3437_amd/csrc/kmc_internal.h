@@ -26,8 +26,10 @@ struct alignas(16) BoxDev {
     double D2, dt, R, R2;
     int32_t nc[3];
     int32_t periodic[3];
+    int32_t absorb[3];   // absorbing faces per axis
     int32_t sphere;
-    uint32_t coff;       // first global cell of the box
+    uint32_t coff;       // first global cell of the box (its nc[0]*nc[1]*nc[2] grid cells are
+                         // followed by one cell for the particles absorbed so far)
     uint32_t poff;       // first global particle index of the box
     uint32_t n;          // particles in the box
     // FP32 screen constants
@@ -42,6 +44,10 @@ struct alignas(16) BoxDev {
     // (hi_k - lo_k) / nc_k, time the simulated time since initialisation
     double dx, dt_cap, time;
 };
+
+// Flag on a particle id (ids stay below 2^31): the particle was absorbed by
+// an absorbing face and has left the gas.
+constexpr uint32_t kGone = 0x80000000u;
 
 // Cell-sorted FP64 particle record (48 bytes, 16-byte aligned).
 struct alignas(16) P64 {
@@ -62,12 +68,11 @@ struct Ctl {
     unsigned long long rechecks_total;  // FP32 screen: particles re-searched
     unsigned long long fallbacks_total; // FP32 screen: list overflows
     unsigned long long scratch;         // target of host-requested reductions
-    unsigned long long candidates_total;// candidates recorded by the search (sum over steps)
+    unsigned long long absorbed_total;  // particles absorbed by absorbing faces so far
     unsigned int recheck_count;         // this step's recheck list length
     unsigned int overflow;              // this step's overflow flag
-    unsigned int work_next;             // work-queue head of persistent kernels
     unsigned int ovf_count;             // this step's overflow pair list length
-    unsigned int pad_[2];
+    unsigned int pad_[3];
 };
 
 // FP32 screen thresholds of one box for one step, affine in the pair's g2:

@@ -44,6 +44,7 @@ class Box:
     ncell: tuple
     periodic: tuple = (False, False, False)
     sphere: bool = False
+    absorb: tuple = (False, False, False)   # absorbing faces per axis (not periodic)
     R: float = 0.0
     D2: float = 0.0
     dt: float = 0.0

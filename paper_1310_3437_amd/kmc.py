@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libkmc.so")
 KMC_OK, KMC_EINVAL, KMC_ENOMEM, KMC_EDEVICE, KMC_EOVERFLOW, KMC_ESTATE = 0, -1, -2, -3, -4, -5
 KMC_FP64, KMC_FP32_SCREEN = 0, 1
 KMC_GEOM_BOX, KMC_GEOM_SPHERE = 0, 1
-KMC_BC_REFLECT, KMC_BC_PERIODIC = 0, 1
+KMC_BC_REFLECT, KMC_BC_PERIODIC, KMC_BC_ABSORB = 0, 1, 2
 KMC_KIN_AT_TSTAR, KMC_KIN_VEL_ONLY = 0, 1
 KMC_DT_FIXED, KMC_DT_ADAPTIVE = 0, 1
 KMC_SEARCH_HALF, KMC_SEARCH_FULL = 0, 1
@@ -73,6 +73,7 @@ class KmcStats(C.Structure):
         ("timed_steps", C.c_uint64),
         ("search_kernel_ms", C.c_double),
         ("candidates", C.c_uint64),
+        ("absorbed", C.c_uint64),
     ]
 
 
@@ -153,7 +154,8 @@ def make_boxes(boxes):
         kb.geometry = KMC_GEOM_SPHERE if b.sphere else KMC_GEOM_BOX
         inv_h = b.inv_h
         for a in range(3):
-            kb.bc[a] = KMC_BC_PERIODIC if b.periodic[a] else KMC_BC_REFLECT
+            absorb = getattr(b, "absorb", (False, False, False))[a]
+            kb.bc[a] = KMC_BC_ABSORB if absorb else (KMC_BC_PERIODIC if b.periodic[a] else KMC_BC_REFLECT)
             kb.ncell[a] = int(b.ncell[a])
             kb.lo[a] = float(b.lo[a])
             kb.hi[a] = float(b.hi[a])
@@ -356,7 +358,7 @@ class Sim:
         _check(load().kmc_get_stats(self._ctx, C.byref(s), self._stream()), "kmc_get_stats")
         return dict(steps=s.steps, n_total=s.n_total, cells_total=s.cells_total, rechecks=s.rechecks,
                     fallbacks=s.fallbacks, timed_steps=s.timed_steps, search_kernel_ms=s.search_kernel_ms,
-                    candidates=s.candidates,
+                    candidates=s.candidates, absorbed=s.absorbed,
                     ms={PHASES[k]: s.ms[k] for k in range(len(PHASES))})
 
     def close(self):

@@ -33,7 +33,7 @@ def test_struct_sizes_match_header():
     # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes
     assert C.sizeof(kmc.KmcBox) == 128
     assert C.sizeof(kmc.KmcConfig) == 80
-    assert C.sizeof(kmc.KmcStats) == 128
+    assert C.sizeof(kmc.KmcStats) == 136
 
 
 def _ws(boxes, **cfg):
@@ -69,6 +69,8 @@ def _good():
     lambda b: setattr(b, "hi", (-0.5, 1, 1)),          # negative extent
     lambda b: setattr(b, "D2", 0.3 ** 2),              # cell edge 0.25 < D
     lambda b: (setattr(b, "sphere", True), setattr(b, "R", 0.5)),   # sphere with periodic axes
+    lambda b: (setattr(b, "periodic", (False,) * 3), setattr(b, "absorb", (True, False, False)),
+               setattr(b, "sphere", True), setattr(b, "R", 0.5)),   # absorbing faces need a box
 ])
 def test_invalid_boxes_rejected(mutate):
     b = _good()
@@ -136,3 +138,11 @@ def test_planar_mode_needs_one_reflecting_z_layer():
     import dataclasses
     per = dataclasses.replace(w.boxes[0], periodic=(True, True, True), ncell=(50, 50, 3))
     assert _ws([per], dims=2)[0] == kmc.KMC_EINVAL
+
+
+def test_absorbing_faces_accepted_and_one_extra_cell_per_box():
+    b = _good()
+    b.periodic = (False, True, True)
+    b.absorb = (True, False, False)
+    rc, n1 = _ws([b])
+    assert rc == 0

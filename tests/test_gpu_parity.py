@@ -66,6 +66,7 @@ def run_parity(kmc, w, steps, check_every=1, precision="fp64", **cfg):
     dt, tm = sim.time()
     assert list(dt) == ref.dt_last and list(tm) == ref.time, "time steps differ"
     stats = sim.stats()
+    assert stats["absorbed"] == ref.absorbed(), (stats["absorbed"], ref.absorbed())
     print(f"[parity] ok exact={exact} rechecks={stats['rechecks']} fallbacks={stats['fallbacks']}", flush=True)
     sim.close()
     run_parity.last_stats = stats
@@ -281,3 +282,21 @@ def test_planar_mode(kmc, precision, mode):
     assert np.all(st[2] == 0.5) and np.all(st[5] == 0.0)
     w = _adaptive(I.c1_planar(n=50_000, D=0.004, steps=3), 0.5, 10.0)
     run_parity(kmc, w, 3, precision=precision, search_mode=sm, use_graph=True)
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_absorbing_faces(kmc, precision, mode):
+    """Absorbing faces (Section 1): particles beyond them leave the gas; they
+    no longer search, collide or move, and their last state is kept."""
+    import dataclasses
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    w = I.c2_shock(n=40_000, steps=12)
+    w.boxes = [dataclasses.replace(b, absorb=(True, False, False)) for b in w.boxes]
+    run_parity(kmc, w, 12, precision=precision, search_mode=sm)
+    assert run_parity.last_stats["absorbed"] > 0
+    # periodic y and z, absorbing x, adaptive step, graph replay
+    w = _adaptive(I.c1_small(steps=6), 1.0, 10.0)
+    w.boxes = [dataclasses.replace(b, periodic=(False, True, True), absorb=(True, False, False)) for b in w.boxes]
+    run_parity(kmc, w, 6, precision=precision, search_mode=sm, use_graph=True)
+    assert run_parity.last_stats["absorbed"] > 0

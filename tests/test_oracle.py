@@ -630,3 +630,78 @@ def test_planar_collision_rate_matches_kinetic_theory():
         got += acc // 2
     expect = expect_per_seed * seeds
     assert abs(got / expect - 1.0) < 0.02, (got, expect)
+
+
+# --------------------------------------------------------------------------
+# Absorbing faces (Section 1 names absorptive boxes beside reflective and
+# periodic ones)
+# --------------------------------------------------------------------------
+
+def _abs_box(n, dt=0.1, D=0.01, periodic=(False, False, False), absorb=(True, False, False), nc=10):
+    return I.Box(n=n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), ncell=(nc, nc, nc), periodic=periodic,
+                 absorb=absorb, D2=D * D, dt=dt)
+
+
+def test_absorbed_particle_leaves_and_stays():
+    s = np.zeros((6, 3))
+    s[:, 0] = (0.05, 0.5, 0.5, -1.0, 0.0, 0.0)     # crosses lo in this step
+    s[:, 1] = (0.10, 0.2, 0.2, -1.0, 0.0, 0.0)     # reaches lo exactly: stays (strict)
+    s[:, 2] = (0.90, 0.8, 0.8, 2.0, 0.0, 0.0)      # crosses hi
+    w = I.Workload("abs", [_abs_box(3)], s.copy(), 2)
+    r = O.Run(w)
+    r.step()
+    st = r.full_state()
+    assert list(r.gone[0]) == [1, 0, 1]
+    assert st[0, 0] == 0.05 + (-1.0) * 0.1 and st[0, 2] == 0.90 + 2.0 * 0.1
+    assert st[0, 1] == 0.0
+    frozen = st.copy()
+    r.step()
+    st2 = r.full_state()
+    assert np.array_equal(st2[:, [0, 2]], frozen[:, [0, 2]])
+    assert r.gone[0][1] == 1 and st2[0, 1] == -0.1 and r.absorbed() == 3
+
+
+def test_absorbed_particles_do_not_collide():
+    # B heads for A's frozen position beyond the face; A has left the gas
+    s = np.zeros((6, 2))
+    s[:, 0] = (0.02, 0.5, 0.5, -1.0, 0.0, 0.0)
+    s[:, 1] = (0.30, 0.5, 0.5, -1.0, 0.0, 0.0)
+    box = _abs_box(2, dt=0.05, D=0.3)
+    w = I.Workload("abs2", [box], s.copy(), 3)
+    r = O.Run(w)
+    r.step()
+    assert list(r.gone[0]) == [1, 0]
+    for _ in range(3):
+        npairs, _ = r.step()
+        assert npairs == 0 and r.partner_by_id[1] == -1
+
+
+def test_absorbed_fraction_matches_free_flight():
+    """One step of a collisionless gas, uniform in the unit cube with a
+    standard normal velocity, two absorbing x faces: the expected absorbed
+    fraction is 2 dt E[max(0, v_x)] = 2 dt / sqrt(2 pi)."""
+    N, dt = 400_000, 0.01
+    rng = np.random.default_rng(31)
+    s = np.empty((6, N))
+    s[0:3] = rng.random((3, N))
+    s[3:6] = rng.standard_normal((3, N))
+    box = _abs_box(N, dt=dt, D=1e-6, periodic=(False, True, False), nc=60)
+    r = O.Run(I.Workload("flux", [box], s, 1))
+    npairs, _ = r.step()
+    assert npairs == 0
+    expect = N * 2.0 * dt / math.sqrt(2.0 * math.pi)
+    got = r.absorbed()
+    assert abs(got - expect) < 4.0 * math.sqrt(expect), (got, expect)
+    # exactly those that crossed a face
+    x_end = s[0] + s[3] * dt
+    assert got == int(((x_end < 0.0) | (x_end > 1.0)).sum())
+
+
+def test_absorbing_axes_are_validated():
+    s = np.zeros((6, 1))
+    bad = I.Box(n=1, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(10, 10, 10), periodic=(True, False, False),
+                absorb=(True, False, False), D2=1e-4, dt=0.1)
+    with pytest.raises(ValueError):
+        O.step_box(bad, s.copy(), np.zeros(1, np.uint32), 0, gone=np.zeros(1, np.uint8))
+    with pytest.raises(ValueError):     # absorbing faces need the gone flags
+        O.step_box(_abs_box(1), s.copy(), np.zeros(1, np.uint32), 0)
