@@ -341,16 +341,31 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* l
     return excl;
 }
 
+// The eight counts of cells base..base+7 (zero beyond the last cell), with
+// two 16-byte loads when all eight exist.
+__device__ __forceinline__ void load_counts(const Plan& p, uint32_t base, uint32_t v[kScanItems])
+{
+    static_assert(kScanItems == 8, "two uint4 per thread");
+    if (base + kScanItems <= p.C) {
+        const uint4* cp = reinterpret_cast<const uint4*>(p.count + base);
+        const uint4 a = cp[0], b = cp[1];
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) v[k] = base + k < p.C ? p.count[base + k] : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Plan p)
 {
     __shared__ uint32_t lds[kScanBlock / 64 + 1];
     const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    load_counts(p, base, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t c = base + k;
-        if (c < p.C) s += p.count[c];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t total;
     block_exclusive_scan(s, lds, total);
     if (threadIdx.x == 0) p.partial[blockIdx.x] = total;
@@ -383,23 +398,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
     __shared__ uint32_t lds[kScanBlock / 64 + 1];
     const uint32_t base = blockIdx.x * (uint32_t)kScanTile + threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
+    load_counts(p, base, v);
     uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t c = base + k;
-        v[k] = c < p.C ? p.count[c] : 0u;
-        s += v[k];
-    }
+    for (int k = 0; k < kScanItems; ++k) s += v[k];
     uint32_t total;
     uint32_t run = block_exclusive_scan(s, lds, total) + p.partial[blockIdx.x];
+    uint32_t st[kScanItems];
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
-        const uint32_t c = base + k;
-        if (c < p.C) {
-            p.start[c] = run;
-            p.count[c] = 0u;
-        }
+        st[k] = run;
         run += v[k];
+    }
+    if (base + kScanItems <= p.C) {
+        // 32-byte aligned runs of eight cells (the arrays are 256-byte aligned)
+        uint4* sp = reinterpret_cast<uint4*>(p.start + base);
+        uint4* cp = reinterpret_cast<uint4*>(p.count + base);
+        sp[0] = make_uint4(st[0], st[1], st[2], st[3]);
+        sp[1] = make_uint4(st[4], st[5], st[6], st[7]);
+        cp[0] = make_uint4(0u, 0u, 0u, 0u);
+        cp[1] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const uint32_t c = base + k;
+            if (c < p.C) {
+                p.start[c] = st[k];
+                p.count[c] = 0u;
+            }
+        }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) p.start[p.C] = p.N;
 }
@@ -1335,14 +1362,69 @@ __global__ __launch_bounds__(256) void k_finish(Plan p)
     if (valid) p.partner[i] = best;
 }
 
-// FP64 re-search of the particles the screen left undecided.
+// The FP64 search of one particle by a whole wave: the lanes share its
+// candidates and the wave takes the (key, id) minimum of their minima.  All
+// lanes of the wave must call it with the same i; returns the partner in
+// every lane.
+__device__ int32_t search_one64_wave(const Plan& p, uint32_t i)
+{
+    if (p.idB[i] & kGone) return -1;
+    const int lane = threadIdx.x & 63;
+    const BoxDev& B = box_of(p, i);
+    const P64* __restrict__ X = p.B;
+    const P64 me = X[i];
+    const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
+    const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
+    const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
+    const double D2 = B.D2, dt = B.dt;
+    double best_key = __builtin_inf();
+    uint32_t best_id = 0xFFFFFFFFu;
+    int32_t best = -1;
+    for_each_range(B, cx, cy, cz, p.start, [&](uint32_t s, uint32_t e, int wx, int wy, int wz) {
+        const bool shift = (wx | wy | wz) != 0;
+        const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
+        for (uint32_t j = s + (uint32_t)lane; j < e; j += 64u) {
+            const P64 q = X[j];
+            double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
+            if (shift) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            if (accept(pq, D2, dt)) {
+                const double key = pq.c2 / pq.g2;
+                const uint32_t idj = p.idB[j];
+                if (key < best_key || (key == best_key && idj < best_id)) {
+                    best_key = key;
+                    best_id = idj;
+                    best = (int32_t)j;
+                }
+            }
+        }
+    });
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double k2 = __shfl_xor(best_key, off, 64);
+        const uint32_t id2 = (uint32_t)__shfl_xor((int)best_id, off, 64);
+        const int32_t b2 = __shfl_xor(best, off, 64);
+        if (k2 < best_key || (k2 == best_key && id2 < best_id)) {
+            best_key = k2;
+            best_id = id2;
+            best = b2;
+        }
+    }
+    return best;
+}
+
+// FP64 re-search of the particles whose candidate lists overflowed, one
+// wave per particle.
 __global__ void k_recheck64(Plan p)
 {
     const uint32_t cnt = p.ctl->recheck_count;
     const uint32_t n = cnt < p.recheck_cap ? cnt : p.recheck_cap;
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    for (uint32_t k = wave; k < n; k += nwaves) {
         const uint32_t i = p.recheck[k];
-        p.partner[i] = search_one64(p, i);
+        const int32_t b = search_one64_wave(p, i);
+        if ((threadIdx.x & 63) == 0) p.partner[i] = b;
     }
 }
 
