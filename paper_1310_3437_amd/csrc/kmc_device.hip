@@ -829,12 +829,14 @@ struct PolF64 {
     {
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         const double D2 = B.D2, dt = B.dt;
-        for (uint32_t j = j0; j < j1; ++j) {
-            const P64 q = l.rec[j - c0];
+        const P64* rp = l.rec + (j0 - c0);
+        const P64* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
+        for (; rp < re; ++rp) {
+            const P64 q = *rp;
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            if (accept(pq, D2, dt)) f.add(p, i, j, wcode(wx, wy, wz));
+            if (accept(pq, D2, dt)) f.add(p, i, c0 + (uint32_t)(rp - l.rec), wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: running (key, id) minimum over the acceptable pairs
@@ -940,14 +942,27 @@ __device__ __forceinline__ void screen_thresholds(const BoxDev& B, const double 
     const double f = (double)guard * (1.0 + 1e-5) * (1.0 + 1e-6);
     double t[8];
     screen_bound(u, er, Rk, eg, B.D2, B.dt, G0, f, t);
+    // thresholds rounded to FP32 stay above the bounds (f carries 1e-5 of slack)
     g.tb0 = (float)t[0];
     g.tb1 = (float)t[1];
     g.tt0 = (float)t[2];
     g.tt1 = (float)t[3];
     g.tc0 = (float)t[4];
     g.tc1 = (float)t[5];
-    g.tg0 = (float)t[6];
-    g.tg1 = (float)t[7];
+    // Folded constants, rounded up (the factor 1 + 2e-6 exceeds every rounding
+    // here).  m2: -b - kdt g2 <= -b - (dt + tt1) g2 for kdt >= dt + tt1, and the
+    // screen's one rounding of the FMA is monotone.  m3: replacing the
+    // subtrahend D2 of the screen's fl(|r|^2 - D2) by kD2 lowers that value by
+    // at least kD2 - D2 - u (|fl(|r|^2) - kD2| + |fl(|r|^2) - D2|), which is >= tc1
+    // when kD2 (1 - u) >= D2 (1 + u) + tc1 + 2 u RRb with RRb >= fl(|r|^2).
+    // Without bounds (guard 0) the constants are the criteria's own.
+    const double dt32 = (double)B.dt_32, D2_32 = (double)B.D2_32;
+    double RRb = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) RRb += (Rk[k] + er[k]) * (Rk[k] + er[k]);
+    RRb *= 1.0 + 1e-5;
+    g.kdt = t[3] > 0.0 ? (float)((dt32 + t[3]) * (1.0 + 2e-6)) : B.dt_32;
+    g.kD2 = t[5] > 0.0 ? (float)((D2_32 + t[5] + 2.0 * u * (RRb + D2_32 + t[5])) * (1.0 + 2e-6)) : B.D2_32;
 }
 
 __global__ void k_screen_bounds(Plan p)
@@ -1035,20 +1050,23 @@ struct PolF32 {
                                 const Own& o, const BoxDev& B, const Group& g, int wx, int wy, int wz, int, int,
                                 Found& f)
     {
-        const float D2 = B.D2_32, dt = B.dt_32;
-        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, tt1 = g.t.tt1, tc0 = g.t.tc0, tc1 = g.t.tc1;
-        for (uint32_t j = j0; j < j1; ++j) {
-            const float4 qa = l.r[j - c0].a;
-            const float2 qb = l.r[j - c0].b;
+        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
+        // the loop steps an LDS pointer only (the sorted index is derived
+        // from it for the rare kept pair)
+        const Rec32* rp = l.r + (j0 - c0);
+        const Rec32* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
+        for (; rp < re; ++rp) {
+            const float4 qa = rp->a;
+            const float2 qb = rp->b;
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const float m2 = fmaf(-dt, g2, -b);
-            const float m3 = fmaf(rr - D2, g2, -(b * b));
-            const float Tb = fmaf(tb1, g2, tb0), Tt = fmaf(tt1, g2, tt0), Tc = fmaf(tc1, g2, tc0);
-            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc)) f.add(p, i, j, wcode(wx, wy, wz));
+            const float mb = fmaf(-tb1, g2, b);
+            const float m2 = fmaf(-kdt, g2, -b);
+            const float m3 = fmaf(rr - kD2, g2, -(b * b));
+            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0)) f.add(p, i, c0 + (uint32_t)(rp - l.r), wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: every pair the screen cannot reject is decided in
@@ -1058,8 +1076,7 @@ struct PolF32 {
                                      uint32_t j1, uint32_t i, const Own& o, const BoxDev& B, const Group& g,
                                      int wx, int wy, int wz, int, int, Best& best)
     {
-        const float D2 = B.D2_32, dt = B.dt_32;
-        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, tt1 = g.t.tt1, tc0 = g.t.tc0, tc1 = g.t.tc1;
+        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
         for (uint32_t j = j0; j < j1; ++j) {
             const float4 qa = l.r[j - c0].a;
             const float2 qb = l.r[j - c0].b;
@@ -1068,10 +1085,10 @@ struct PolF32 {
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const float m2 = fmaf(-dt, g2, -b);
-            const float m3 = fmaf(rr - D2, g2, -(b * b));
-            const float Tb = fmaf(tb1, g2, tb0), Tt = fmaf(tt1, g2, tt0), Tc = fmaf(tc1, g2, tc0);
-            if ((b <= Tb) & (m2 <= Tt) & (m3 <= Tc) & (j != i)) {
+            const float mb = fmaf(-tb1, g2, b);
+            const float m2 = fmaf(-kdt, g2, -b);
+            const float m3 = fmaf(rr - kD2, g2, -(b * b));
+            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i)) {
                 const P64 me = p.B[i], q = p.B[j];
                 double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
                 if (SH) {

@@ -75,12 +75,15 @@ struct Ctl {
     unsigned int pad_[3];
 };
 
-// FP32 screen thresholds of one box for one step, affine in the pair's g2:
-// reject when b > tb0 + tb1 g2, -b - dt g2 > tt0 + tt1 g2 or
-// (|r|^2 - D2) g2 - b^2 > tc0 + tc1 g2; accept for certain when all three are
-// below minus their bound and g2 > tg0 + tg1 g2.
+// FP32 screen thresholds of one box for one step.  The bounds on the error
+// of the screen's b, m2 = -b - dt g2 and m3 = (|r|^2 - D2) g2 - b^2 are affine
+// in the pair's g2 (t0 + t1 g2); the g2 terms are folded into the tests'
+// constants, so a pair is kept when
+//   b - tb1 g2 <= tb0,  -b - kdt g2 <= tt0,  (|r|^2 - kD2) g2 - b^2 <= tc0
+// with kdt >= dt + tt1 and kD2 >= D2 + tc1 plus the rounding of |r|^2 - kD2.
+// tt1 and tc1 are kept for reference.
 struct alignas(16) ScreenBounds {
-    float tb0, tb1, tt0, tt1, tc0, tc1, tg0, tg1;
+    float tb0, tb1, tt0, kdt, tc0, kD2, tt1, tc1;
 };
 
 // Device pointers carved out of the caller's workspace plus launch scalars.
