@@ -14,7 +14,7 @@ dominant kernel (the partner search).  `cpu_baseline` times the CPU oracle
 (test infrastructure) on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
-                    [--workload c3_sphere|c2_shock|c4_batch|c5_blobs] [--dt-rule adaptive]
+                    [--workload c3_sphere|c2_shock|c4_batch|c5_blobs|c6_mixture] [--dt-rule adaptive]
 
 The other workloads (shock tube, 256-box batch, Gaussian blobs) print the same
 line for their own configuration; the headline is c3_sphere.
@@ -74,9 +74,10 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests, search_mode=0):
     import torch
     name = "fp64" if precision == kmc.KMC_FP64 else "fp32_screen"
     log(f"[bench] {name}: init N={w.n}")
+    kinds = None if w.species is None else (w.species, w.radius, w.mass)
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=precision,
                   history=max(64, steps + warmup), profile=True, dt_rule=w.dt_rule,
-                  dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search_mode)
+                  dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search_mode, kinds=kinds)
     sim.step(warmup)
     torch.cuda.synchronize()
     s0 = sim.stats()
@@ -130,6 +131,12 @@ def workload(name, n, dt_rule):
         b = w.boxes[0]
         desc = (f"c5_blobs: N={n:.0e} in 64 Gaussian blobs, periodic unit cube, D={w.info['D']:.2e}, "
                 f"{b.ncell[0]}^3 cells, dt={b.dt:.4e}")
+    elif name == "c6_mixture":
+        w = inputs.c6_mixture(n=n)
+        b = w.boxes[0]
+        desc = (f"c6_mixture: N={n:.0e} three kinds (radius 1:2:3, mass 1:4:9, fractions 0.5/0.3/0.2), "
+                f"periodic unit cube, Maxwellian at one temperature, {b.ncell[0]}^3 cells "
+                f"(edge {b.h[0]:.5f} >= largest pair diameter {2 * max(w.radius):.5f}), dt={b.dt:.4e}")
     else:
         raise SystemExit(f"bench.py: unknown workload {name}")
     if dt_rule == "adaptive":
@@ -148,6 +155,8 @@ def cpu_workload(name, n_sample):
         return inputs.c2_shock(n=n_sample, steps=1), f"the c2_shock recipe at N={n_sample:.0e}"
     if name == "c4_batch":
         return inputs.c4_batch(nboxes=64, steps=1), "the first 64 boxes of the c4_batch recipe"
+    if name == "c6_mixture":
+        return inputs.c6_mixture(n=n_sample, steps=1), f"the c6_mixture recipe at N={n_sample:.0e}"
     return inputs.c5_blobs(n=n_sample, steps=1), f"the c5_blobs recipe at N={n_sample:.0e} (same particles per cell)"
 
 
@@ -240,8 +249,8 @@ def main():
     if args.ppc_sweep:
         ppc_sweep(kmc, args)
         return
-    full = dict(c3_sphere=1e8, c2_shock=1e6, c4_batch=None, c5_blobs=1e7)
-    sample = dict(c3_sphere=1e7, c2_shock=1e6, c4_batch=None, c5_blobs=3e5)
+    full = dict(c3_sphere=1e8, c2_shock=1e6, c4_batch=None, c5_blobs=1e7, c6_mixture=1e8)
+    sample = dict(c3_sphere=1e7, c2_shock=1e6, c4_batch=None, c5_blobs=3e5, c6_mixture=1e7)
     if args.workload not in full:
         raise SystemExit(f"bench.py: unknown workload {args.workload}")
     n_arg = args.n if args.n is not None else full[args.workload]
@@ -297,8 +306,9 @@ def main():
             "path": head_name,
         },
         "roofline": {
-            "kernel": f"k_search_{args.search}<" + ("PolF32> (FP32 screen)" if head_name == "fp32_screen"
-                                                   else "PolF64> (FP64)"),
+            "kernel": f"k_search_{args.search}<" + ("PolF32" if head_name == "fp32_screen" else "PolF64")
+                      + ("<true>>" if w.species is not None else "<false>>")
+                      + (" (FP32 screen)" if head_name == "fp32_screen" else " (FP64)"),
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_VALU_TFLOPS,

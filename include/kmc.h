@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define KMC_ABI_VERSION 2
+#define KMC_ABI_VERSION 3
 
 typedef enum {
     KMC_OK = 0,
@@ -107,6 +107,42 @@ typedef struct kmc_box {
     double dt;
 } kmc_box;
 
+/* Kinds of particles (species).  Section 1 gives every particle its own
+ * mass and effective radius, and a candidate must be within the effective
+ * radii of the searcher.  With species, particle i is of kind s_i:
+ *   - a pair (i, j) is within each other's effective radii when its distance
+ *     of closest approach is below radius[s_i] + radius[s_j]: the criterion
+ *     c2 < D2_ij * g2 uses D2_ij = d * d with d = radius[s_i] + radius[s_j]
+ *     in binary64, in place of the box's D2 (which is then not used in the
+ *     criterion, but is still validated);
+ *   - the ordering key is unchanged (the squared distance of closest
+ *     approach c2 / g2);
+ *   - a colliding pair with equal masses scatters as without species; with
+ *     masses m_a != m_b (a the smaller id) M = m_a + m_b,
+ *     v_cm,k = fma(m_a, v_a,k, m_b * v_b,k) / M, |g| = sqrt(g2), and a and b
+ *     leave with v_cm + ((m_b / M) * |g|) n and v_cm - ((m_a / M) * |g|) n
+ *     (momentum and kinetic energy are kept);
+ *   - every box's cell edge must be >= the largest pair diameter
+ *     2 * max(radius) on every axis.
+ * Fields:
+ *   count      kinds, 1..KMC_MAX_SPECIES;
+ *   reserved   must be zero;
+ *   radius[s]  effective radius of kind s (finite, > 0), s < count;
+ *   mass[s]    mass of kind s (finite, > 0), s < count;
+ *   d_kind     device pointer, n_total bytes in id order (box offsets as for
+ *              the state): the kind of each particle, < count; read once
+ *              during kmc_init (an entry >= count makes kmc_init fail with
+ *              KMC_EINVAL).
+ * The structure is read during kmc_workspace_bytes and kmc_init only. */
+#define KMC_MAX_SPECIES 8
+typedef struct kmc_species {
+    uint32_t count;
+    uint32_t reserved;
+    double radius[KMC_MAX_SPECIES];
+    double mass[KMC_MAX_SPECIES];
+    const uint8_t* d_kind;
+} kmc_species;
+
 /* Run configuration.  Zero-initialise and set what you need. */
 typedef struct kmc_config {
     uint64_t seed;             /* Philox key word 0                                      */
@@ -139,6 +175,9 @@ typedef struct kmc_config {
                                   bounds (testing only: the screen is then not exact)     */
     double dt_factor;          /* KMC_DT_ADAPTIVE: the factor C below; 0 = 1 (the paper's
                                   rule), otherwise finite and > 0                         */
+    const kmc_species* species; /* NULL: one kind of particle (each box's D2, equal
+                                   masses); otherwise the kinds described above (host
+                                   pointer, read by kmc_workspace_bytes and kmc_init)   */
 } kmc_config;
 
 /* Time step rules.
@@ -206,7 +245,8 @@ int kmc_workspace_bytes(const kmc_box* boxes, uint32_t nboxes, const kmc_config*
  *                  owned by the caller, untouched by anyone else until
  *                  kmc_destroy;
  *   out            receives the context.
- * Errors: KMC_EINVAL (bad box or config, null pointer, misaligned workspace),
+ * Errors: KMC_EINVAL (bad box or config, null pointer, misaligned workspace,
+ * a particle kind >= species->count),
  * KMC_ENOMEM (workspace too small), KMC_EOVERFLOW (more than 2^31-1 particles
  * or 2^32-2 cells in total), KMC_EDEVICE. */
 int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg,

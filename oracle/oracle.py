@@ -33,6 +33,11 @@ class OrcBox(C.Structure):
         ("D2", C.c_double),
         ("dt", C.c_double),
         ("seed", C.c_uint64),
+        ("nspecies", C.c_int32),
+        ("pad_", C.c_int32),
+        ("species", C.POINTER(C.c_uint8)),
+        ("radius", C.POINTER(C.c_double)),
+        ("mass", C.POINTER(C.c_double)),
     ]
 
 
@@ -94,10 +99,22 @@ def _ptr(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def make_box(box, seed=1, kinematics=0, dims=3):
+def make_box(box, seed=1, kinematics=0, dims=3, kinds=None):
     """OrcBox from a paper_1310_3437_amd.inputs.Box (or any object with the
-    same attributes)."""
+    same attributes).  kinds = (species, radius, mass): per-particle kind
+    (uint8, the box's particles) and per-kind effective radius and mass, or
+    None for one kind of particle."""
     ob = OrcBox()
+    if kinds is not None:
+        sp, rad, mass = kinds
+        sp = np.ascontiguousarray(sp, dtype=np.uint8)
+        rad = np.ascontiguousarray(rad, dtype=np.float64)
+        mass = np.ascontiguousarray(mass, dtype=np.float64)
+        ob.nspecies = int(rad.shape[0])
+        ob.species = _ptr(sp, C.c_uint8)
+        ob.radius = _ptr(rad, C.c_double)
+        ob.mass = _ptr(mass, C.c_double)
+        ob._keep = (sp, rad, mass)   # the arrays live as long as the structure
     ob.n = int(box.n)
     ob.sphere = 1 if box.sphere else 0
     for k in range(3):
@@ -142,13 +159,13 @@ def pair(box, pi, pj, wrap=(0, 0, 0)):
     return dict(r=tuple(q.r), g=tuple(q.g), b=q.b, g2=q.g2, c2=q.c2, key=q.key, acc=bool(q.acc))
 
 
-def find_partners(box, state, ids=None, nthreads=0, brute=False):
+def find_partners(box, state, ids=None, nthreads=0, brute=False, kinds=None):
     """Partner array (indices into the box's particles, -1 for none)."""
     s = _soa(state)
     n = s.shape[1]
     ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     out = np.empty(n, dtype=np.int32)
-    ob = make_box(box)
+    ob = make_box(box, kinds=kinds)
     ob.n = n
     if brute:
         rc = lib().orc_find_partners_bruteforce(C.byref(ob), _ptr(s, C.c_double), _ptr(ids, C.c_uint32),
@@ -212,7 +229,7 @@ def adaptive_dt(box, state, factor=1.0, gone=None):
     return float(out.value)
 
 
-def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, dims=3):
+def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, dims=3, kinds=None):
     """The oracle step of one box evaluated at the particles `sel` only
     (indices into the box); `state` is not modified.  Returns (partner
     indices of the selected particles, their (6, len(sel)) post-step state)."""
@@ -220,7 +237,7 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, d
     n = s.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
-    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds)
     ob.n = n
     partner = np.empty(len(sel), dtype=np.int32)
     out = np.empty((len(sel), 6), dtype=np.float64)
@@ -232,15 +249,15 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, d
     return partner, out.T.copy()
 
 
-def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, gone=None):
+def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, gone=None, kinds=None):
     """One oracle step of one box, in place on `state` ((6, n) float64,
     C-contiguous) and on `gone` (uint8 per particle, 1 = absorbed; required
-    with absorbing faces).  Returns (partner indices, npairs, digest,
-    pair_tests)."""
+    with absorbing faces).  kinds as in make_box.  Returns (partner indices,
+    npairs, digest, pair_tests)."""
     assert state.dtype == np.float64 and state.flags.c_contiguous and state.shape[0] == 6
     n = state.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
-    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds)
     ob.n = n
     partner = np.empty(n, dtype=np.int32)
     npairs = C.c_uint64(0)
@@ -292,7 +309,7 @@ class Run:
             p, npairs, dig, t = step_box(box, self.state[b], self.ids[b], self.step_index,
                                          seed=self.w.seed, kinematics=self.w.kinematics,
                                          dims=getattr(self.w, "dims", 3), gone=self.gone[b],
-                                         nthreads=self.nthreads)
+                                         nthreads=self.nthreads, kinds=self.kinds(b))
             ids = self.ids[b]
             has = p >= 0
             pb[ids[has]] = ids[p[has]]
@@ -303,6 +320,13 @@ class Run:
         self.pair_tests = tests
         self.step_index += 1
         return tot_pairs, tot_dig
+
+    def kinds(self, b):
+        """(species, radius, mass) of box b's particles, or None for one kind."""
+        sp = getattr(self.w, "species", None)
+        if sp is None:
+            return None
+        return sp[self.off[b]:self.off[b + 1]], self.w.radius, self.w.mass
 
     def absorbed(self):
         """Particles absorbed so far (all boxes)."""

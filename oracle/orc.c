@@ -41,6 +41,15 @@ static int box_ok(const orc_box* b)
     if (b->dims == 2 && (b->ncell[2] != 1 || b->periodic[2] || b->sphere)) return 0;
     for (int k = 0; k < 3; ++k)
         if (b->absorb[k] && (b->periodic[k] || b->sphere)) return 0;
+    if (b->nspecies < 0 || b->nspecies > 8) return 0;
+    if (b->nspecies > 0) {
+        if (!b->radius || !b->mass || (b->n > 0 && !b->species)) return 0;
+        for (int s = 0; s < b->nspecies; ++s)
+            if (!(b->radius[s] > 0.0) || !(b->mass[s] > 0.0) || isinf(b->radius[s]) || isinf(b->mass[s]))
+                return 0;
+        for (int64_t i = 0; i < b->n; ++i)
+            if (b->species[i] >= b->nspecies) return 0;
+    }
     return 1;
 }
 
@@ -87,10 +96,9 @@ static int64_t linear_cell(const orc_box* b, const int32_t c[3])
  * "within the effective radii" (d_min^2 < D2 = sigma/pi) are evaluated
  * multiplied through by g2 > 0:  b <= 0, -b <= dt*g2, c2 < D2*g2.
  * The ordering key of an acceptable candidate is d_min^2 = c2/g2. */
-int orc_pair(const orc_box* b, const double pi[6], const double pj[6],
-             const int32_t wrap[3], orc_pair_q* q)
+static void pair_q(const orc_box* b, const double pi[6], const double pj[6], const int32_t wrap[3], double D2,
+                   orc_pair_q* q)
 {
-    if (!b || !pi || !pj || !wrap || !q) return -1;
     for (int k = 0; k < 3; ++k) {
         double r = pj[k] - pi[k];
         if (wrap[k] != 0) r = r + (double)wrap[k] * (b->hi[k] - b->lo[k]);
@@ -106,9 +114,26 @@ int orc_pair(const orc_box* b, const double pi[6], const double pj[6],
     double cz = fma(r[0], g[1], -(r[1] * g[0]));
     q->c2 = fma(cz, cz, fma(cy, cy, cx * cx));
     q->acc = (q->g2 > 0.0) && (q->b <= 0.0) && (-q->b <= b->dt * q->g2) &&
-             (q->c2 < b->D2 * q->g2);
+             (q->c2 < D2 * q->g2);
     q->key = q->acc ? q->c2 / q->g2 : INFINITY;
+}
+
+int orc_pair(const orc_box* b, const double pi[6], const double pj[6],
+             const int32_t wrap[3], orc_pair_q* q)
+{
+    if (!b || !pi || !pj || !wrap || !q) return -1;
+    pair_q(b, pi, pj, wrap, b->D2, q);
     return 0;
+}
+
+/* Squared interaction diameter of the pair (i, j): D2 for one kind of
+ * particle, else the square of the sum of the two effective radii (hard
+ * spheres touch when their centres are that far apart). */
+static double pair_D2(const orc_box* b, int64_t i, int64_t j)
+{
+    if (b->nspecies == 0) return b->D2;
+    const double d = b->radius[b->species[i]] + b->radius[b->species[j]];
+    return d * d;
 }
 
 static void load6(const double* s, int64_t n, int64_t i, double p[6])
@@ -217,7 +242,7 @@ static int64_t search_one(const orc_box* b, const double* s, const uint32_t* ids
                     ++*tests;
                     load6(s, n, j, pj);
                     orc_pair_q pq;
-                    orc_pair(b, pi, pj, wrap, &pq);
+                    pair_q(b, pi, pj, wrap, pair_D2(b, i, j), &pq);
                     if (!pq.acc) continue;
                     ++*acc_count;
                     if (better(pq.key, ids[j], best_key, best_id)) {
@@ -322,7 +347,7 @@ int orc_find_partners_bruteforce(const orc_box* b, const double* s,
             for (int k = 0; k < 3; ++k) adj &= axis_adjacent(b, k, ci[k], cj[k], &wrap[k]);
             if (!adj) continue;
             orc_pair_q pq;
-            orc_pair(b, pi, pj, wrap, &pq);
+            pair_q(b, pi, pj, wrap, pair_D2(b, i, j), &pq);
             if (pq.acc && better(pq.key, ids[j], best_key, best_id)) {
                 best_key = pq.key;
                 best_id = ids[j];
@@ -510,8 +535,12 @@ int orc_adaptive_dt_ex(const orc_box* b, const double* s, const unsigned char* g
 
 /* Collision of the mutual pair (a, c) with ids[a] < ids[c]: collision time
  * t* (from a's side) and the two new velocities.  Elastic, isotropic scatter
- * of equal masses in the centre-of-mass frame: |g| is kept, its direction is
- * drawn uniformly with the random numbers of the pair's smaller id. */
+ * in the centre-of-mass frame: |g| is kept, its direction is drawn uniformly
+ * with the random numbers of the pair's smaller id.  Equal masses:
+ * v_cm = (v_a + v_c)/2 and each particle moves off at |g|/2 along +-n.
+ * Masses m_a != m_c: v_cm = (m_a v_a + m_c v_c)/M with M = m_a + m_c;
+ * a leaves with v_cm + (m_c/M)|g| n and c with v_cm - (m_a/M)|g| n, which
+ * keeps the momentum and, as |v'_c - v'_a| = |g|, the kinetic energy. */
 static void collide_pair(const orc_box* b, const double* s, const uint32_t* ids,
                          uint64_t step, int64_t a, int64_t c,
                          double nva[3], double nvc[3], double* tstar)
@@ -530,11 +559,27 @@ static void collide_pair(const orc_box* b, const double* s, const uint32_t* ids,
     double nhat[3];
     if (b->dims == 2) orc_direction2(b->seed, step, ids[a], nhat);
     else orc_direction(b->seed, step, ids[a], nhat);
-    double hg = 0.5 * sqrt(q.g2);
-    for (int k = 0; k < 3; ++k) {
-        double vcm = 0.5 * (pa[3 + k] + pc[3 + k]);
-        nva[k] = vcm + hg * nhat[k];
-        nvc[k] = vcm - hg * nhat[k];
+    double ma = 1.0, mc = 1.0;
+    if (b->nspecies > 0) {
+        ma = b->mass[b->species[a]];
+        mc = b->mass[b->species[c]];
+    }
+    if (ma == mc) {
+        double hg = 0.5 * sqrt(q.g2);
+        for (int k = 0; k < 3; ++k) {
+            double vcm = 0.5 * (pa[3 + k] + pc[3 + k]);
+            nva[k] = vcm + hg * nhat[k];
+            nvc[k] = vcm - hg * nhat[k];
+        }
+    } else {
+        double M = ma + mc;
+        double gm = sqrt(q.g2);
+        double wa = (mc / M) * gm, wc = (ma / M) * gm;
+        for (int k = 0; k < 3; ++k) {
+            double vcm = fma(ma, pa[3 + k], mc * pc[3 + k]) / M;
+            nva[k] = vcm + wa * nhat[k];
+            nvc[k] = vcm - wc * nhat[k];
+        }
     }
 }
 

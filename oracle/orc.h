@@ -59,6 +59,17 @@ typedef struct {
     double   D2;           /* squared interaction diameter sigma/pi              */
     double   dt;           /* time step                                         */
     uint64_t seed;         /* Philox key word 0                                 */
+    /* Kinds of particles (Section 1: every particle carries its own mass and
+     * effective radius).  nspecies == 0: one kind, interaction diameter
+     * sqrt(D2), equal masses.  1 <= nspecies <= 8: particle i is of kind
+     * species[i]; a pair (s, t) is within each other's effective radii when
+     * its distance of closest approach is below radius[s] + radius[t] (D2 is
+     * then not used), and it scatters with masses mass[s], mass[t]. */
+    int32_t  nspecies;
+    int32_t  pad_;
+    const uint8_t* species; /* n entries when nspecies > 0                     */
+    const double*  radius;  /* nspecies entries, > 0                           */
+    const double*  mass;    /* nspecies entries, > 0                           */
 } orc_box;
 
 /* Quantities of one ordered pair (searcher i, candidate j). */

@@ -14,9 +14,15 @@
 
 using namespace kmc;
 
+static_assert(sizeof(kmc_box) == 128, "kmc_box layout");
+static_assert(sizeof(kmc_config) == 88, "kmc_config layout");
+static_assert(sizeof(kmc_species) == 144, "kmc_species layout");
+static_assert(KMC_MAX_SPECIES == kMaxKinds, "kind table stride");
+
 struct kmc_ctx {
     Plan plan{};
     kmc_config cfg{};
+    kmc_species species{};   // copy of the caller's kinds (cfg.species points here)
     std::vector<kmc_box> boxes;
     int device = 0;
     bool stepped = false;
@@ -77,7 +83,28 @@ int check_cfg(const kmc_config& c)
     if (c.dt_factor != 0.0 && !finite_pos(c.dt_factor)) return KMC_EINVAL;
     for (int r : c.reserved)
         if (r != 0) return KMC_EINVAL;
+    if (c.species) {
+        const kmc_species& sp = *c.species;
+        if (sp.count < 1 || sp.count > KMC_MAX_SPECIES || sp.reserved != 0) return KMC_EINVAL;
+        for (uint32_t k = 0; k < sp.count; ++k)
+            if (!finite_pos(sp.radius[k]) || !finite_pos(sp.mass[k])) return KMC_EINVAL;
+    }
     return KMC_OK;
+}
+
+// Squared diameter of a pair of kinds: (radius_s + radius_t)^2 in binary64.
+double kinds_D2(const kmc_species& sp, uint32_t s, uint32_t t)
+{
+    const double d = sp.radius[s] + sp.radius[t];
+    return d * d;
+}
+
+double kinds_D2max(const kmc_species& sp)
+{
+    double m = 0.0;
+    for (uint32_t s = 0; s < sp.count; ++s)
+        for (uint32_t t = 0; t < sp.count; ++t) m = std::max(m, kinds_D2(sp, s, t));
+    return m;
 }
 
 struct Totals {
@@ -108,6 +135,13 @@ int validate(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, Total
         for (uint32_t b = 0; b < nboxes; ++b)
             if (boxes[b].ncell[2] != 1 || boxes[b].bc[2] != KMC_BC_REFLECT || boxes[b].geometry != KMC_GEOM_BOX)
                 return KMC_EINVAL;
+    if (cfg->species) {
+        // every neighbour closer than the largest pair diameter lies in the 27 cells
+        const double Dmax = std::sqrt(kinds_D2max(*cfg->species));
+        for (uint32_t b = 0; b < nboxes; ++b)
+            for (int k = 0; k < 3; ++k)
+                if (boxes[b].inv_h[k] * Dmax > 1.0 + 1e-9) return KMC_EINVAL;
+    }
     return totals(boxes, nboxes, t);
 }
 
@@ -155,6 +189,18 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.recheck = (uint32_t*)take(4 * (size_t)(cap ? cap : 1));
     p.ovf = (uint2*)take(sizeof(uint2) * 2 * (N ? N : 1));
     p.cand_acc = (unsigned long long*)take(sizeof(unsigned long long) * kHistLanes);
+    p.nspecies = cfg.species ? (int32_t)cfg.species->count : 0;
+    if (cfg.species) {
+        p.spA = (uint8_t*)take(N ? N : 1);
+        p.spB = (uint8_t*)take(N ? N : 1);
+        p.sp_D2 = (const double*)take(sizeof(double) * kMaxKinds * kMaxKinds);
+        p.sp_mass = (const double*)take(sizeof(double) * kMaxKinds);
+        p.box_kD2 = (float*)take(sizeof(float) * kMaxKinds * kMaxKinds * nboxes);
+    } else {
+        p.spA = p.spB = nullptr;
+        p.sp_D2 = p.sp_mass = nullptr;
+        p.box_kD2 = nullptr;
+    }
     p.N = (uint32_t)N;
     p.C = (uint32_t)C;
     p.nboxes = nboxes;
@@ -282,9 +328,15 @@ int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const
     const size_t need = layout(probe, nullptr, nboxes, *cfg, t);
     if (workspace_bytes < need) return KMC_ENOMEM;
 
+    if (cfg->species && t.N > 0 && !cfg->species->d_kind) return KMC_EINVAL;
     kmc_ctx* c = new (std::nothrow) kmc_ctx();
     if (!c) return KMC_ENOMEM;
     c->cfg = *cfg;
+    if (cfg->species) {
+        c->species = *cfg->species;
+        c->species.d_kind = nullptr;   // read once, below
+        c->cfg.species = &c->species;
+    }
     c->boxes.assign(boxes, boxes + nboxes);
     layout(c->plan, (char*)d_workspace, nboxes, *cfg, t);
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return KMC_EDEVICE; }
@@ -296,16 +348,40 @@ int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const
         coff += (uint64_t)boxes[b].ncell[0] * boxes[b].ncell[1] * boxes[b].ncell[2] + 1u;   // + absorbed cell
         poff += boxes[b].n;
     }
+    // particle kinds: the pair tables, and each box's D2 is the largest pair value
+    std::vector<double> d2tab(kMaxKinds * kMaxKinds, 0.0), mtab(kMaxKinds, 0.0);
+    if (cfg->species) {
+        const kmc_species& sp = *cfg->species;
+        for (uint32_t a = 0; a < sp.count; ++a) {
+            mtab[a] = sp.mass[a];
+            for (uint32_t b2 = 0; b2 < sp.count; ++b2) d2tab[a * kMaxKinds + b2] = kinds_D2(sp, a, b2);
+        }
+        const double D2max = kinds_D2max(sp);
+        for (auto& d : bd) {
+            d.D2 = D2max;
+            d.D2_32 = (float)D2max;
+        }
+    }
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(c->plan.boxes, bd.data(), sizeof(BoxDev) * nboxes, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = launch_init(c->plan, d_state, s);
+    if (e == hipSuccess && cfg->species) {
+        e = hipMemcpyAsync((void*)c->plan.sp_D2, d2tab.data(), sizeof(double) * d2tab.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync((void*)c->plan.sp_mass, mtab.data(), sizeof(double) * mtab.size(), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = launch_init(c->plan, d_state, cfg->species ? cfg->species->d_kind : nullptr, s);
+    unsigned long long bad_kinds = 0;
     if (e == hipSuccess) {
-        // the step counter starts at step0 (k_init_ctl wrote 0)
+        // the step counter starts at step0 (k_init_ctl wrote 0); the kind
+        // check counted its failures in the control block's scratch word
         unsigned long long step0 = cfg->step0;
         e = hipMemcpyAsync(&c->plan.ctl->step, &step0, sizeof(step0), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);   // step0 lives on this stack frame
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&bad_kinds, &c->plan.ctl->scratch, sizeof(bad_kinds), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);   // host buffers live on this stack frame
     }
     if (e != hipSuccess) { delete c; return KMC_EDEVICE; }
+    if (bad_kinds != 0) { delete c; return KMC_EINVAL; }
     *out = c;
     return KMC_OK;
 }

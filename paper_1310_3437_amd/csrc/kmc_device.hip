@@ -199,7 +199,7 @@ __device__ __forceinline__ void block_sum2(uint64_t& a, uint64_t& b, uint64_t* l
 // Initialisation and read-back
 // --------------------------------------------------------------------------
 
-__global__ void k_init_particles(Plan p, const double* __restrict__ in)
+__global__ void k_init_particles(Plan p, const double* __restrict__ in, const uint8_t* __restrict__ kind)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= p.N) return;
@@ -207,6 +207,12 @@ __global__ void k_init_particles(Plan p, const double* __restrict__ in)
 #pragma unroll
     for (int k = 0; k < 6; ++k) p.A[k * N + i] = in[k * N + i];
     p.idA[i] = i;
+    if (p.spA) {
+        // an invalid kind is counted by k_check_kinds (the context is then not
+        // created); it is clamped here so that no table read leaves its table
+        const uint8_t k = kind[i];
+        p.spA[i] = k < (uint8_t)p.nspecies ? k : (uint8_t)(p.nspecies - 1);
+    }
     if (p.boxidx) {
         uint32_t lo = 0, hi = p.nboxes - 1;   // last box with poff <= i
         while (lo < hi) {
@@ -233,6 +239,7 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
         p.ctl->absorbed_total = 0;
+        p.ctl->scratch = 0;
     }
     for (uint32_t k = t; k < (uint32_t)kHistLanes; k += blockDim.x) {
         p.hist_np[k] = 0;
@@ -240,6 +247,16 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
         p.cand_acc[k] = 0;
     }
     for (uint32_t b = t; b < p.nboxes; b += blockDim.x) p.box_v2[b] = 0ull;
+}
+
+// Kinds at or beyond the number of kinds, counted into the control block's
+// scratch word (kmc_init reads it back).
+__global__ void k_check_kinds(Plan p, const uint8_t* __restrict__ kind)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool bad = i < p.N && kind[i] >= (uint8_t)p.nspecies;
+    const uint64_t m = __ballot(bad);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(&p.ctl->scratch, (unsigned long long)__popcll(m));
 }
 
 __global__ void k_read_partners(Plan p, int32_t* __restrict__ out)
@@ -457,6 +474,7 @@ __global__ void k_scatter(Plan p)
         p.B[d] = r;
         const uint32_t id = p.idA[i];
         p.idB[d] = id;
+        if (p.spA) p.spB[d] = p.spA[i];
         if (id & kGone) vx = vy = vz = 0.0;   // not in the gas: no part in the adaptive step
         if (F32) vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
     }
@@ -597,6 +615,19 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
 
 // Exact FP64 search of one particle over its full 27-cell neighbourhood,
 // straight from the sorted records (rechecks, list overflow, fallback).
+// Squared interaction diameter of the pair of sorted particles (i, j): the
+// box's D2 for one kind of particle, else (radius_s + radius_t)^2 of their
+// kinds (row = kMaxKinds * kind of i).
+__device__ __forceinline__ uint32_t kind_row(const Plan& p, uint32_t i)
+{
+    return p.nspecies ? (uint32_t)p.spB[i] * (uint32_t)kMaxKinds : 0u;
+}
+
+__device__ __forceinline__ double pair_D2(const Plan& p, const BoxDev& B, uint32_t row_i, uint32_t j)
+{
+    return p.nspecies ? p.sp_D2[row_i + p.spB[j]] : B.D2;
+}
+
 __device__ int32_t search_one64(const Plan& p, uint32_t i)
 {
     if (p.idB[i] & kGone) return -1;
@@ -606,7 +637,8 @@ __device__ int32_t search_one64(const Plan& p, uint32_t i)
     const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
     const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
     const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
-    const double D2 = B.D2, dt = B.dt;
+    const double dt = B.dt;
+    const uint32_t row = kind_row(p, i);
     double best_key = __builtin_inf();
     uint32_t best_id = 0xFFFFFFFFu;
     int32_t best = -1;
@@ -618,7 +650,7 @@ __device__ int32_t search_one64(const Plan& p, uint32_t i)
             double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
             if (shift) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-            if (accept(pq, D2, dt)) {   // the particle itself has g2 = 0 and is never accepted
+            if (accept(pq, pair_D2(p, B, row, j), dt)) {   // the particle itself has g2 = 0 and is never accepted
                 const double key = pq.c2 / pq.g2;
                 const uint32_t idj = p.idB[j];
                 if (key < best_key || (key == best_key && idj < best_id)) {
@@ -664,13 +696,14 @@ __device__ __forceinline__ void post_candidate(const Plan& p, uint32_t i, uint32
 
 // The definition's exact FP64 decision for the pair (i, j) seen from i (the
 // image from the two cells), and its key when acceptable.
-__device__ __forceinline__ bool exact_key(const Plan& p, const BoxDev& B, const P64& me, uint32_t j, double& key)
+__device__ __forceinline__ bool exact_key(const Plan& p, const BoxDev& B, uint32_t i, const P64& me, uint32_t j,
+                                          double& key)
 {
     const P64 q = p.B[j];
     double r[3];
     rel64(B, me, q, r);
     const PairQ pq = pair_q(r[0], r[1], r[2], q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-    if (!accept(pq, B.D2, B.dt)) return false;
+    if (!accept(pq, pair_D2(p, B, kind_row(p, i), j), B.dt)) return false;
     key = pq.c2 / pq.g2;
     return true;
 }
@@ -714,9 +747,11 @@ struct Found {
     // BATCH records are loaded at a time; SKIP: no loads for empty slots
     // (otherwise branch-free, loading the own record for them) -- measured
     // per precision
-    template <int BATCH, bool SKIP>
+    // K: particles of several kinds (the pair's D2 from the kind table).
+    template <int BATCH, bool SKIP, bool K>
     __device__ __forceinline__ uint32_t flush(const Plan& p, uint32_t i, const P64& me, const BoxDev& B)
     {
+        const uint32_t row = K ? kind_row(p, i) : 0u;
         double key[kReg];
         bool acc[kReg];
 #pragma unroll
@@ -740,7 +775,7 @@ struct Found {
                     if (wy != 0) ry = ry + (double)wy * B.L[1];
                     if (wz != 0) rz = rz + (double)wz * B.L[2];
                     const PairQ pq = pair_q(rx, ry, rz, q[e].vx - me.vx, q[e].vy - me.vy, q[e].vz - me.vz);
-                    acc[k] = k < n && accept(pq, B.D2, B.dt);
+                    acc[k] = k < n && accept(pq, K ? pair_D2(p, B, row, j[k]) : B.D2, B.dt);
                     key[k] = acc[k] ? pq.c2 / pq.g2 : __builtin_inf();
                 }
             }
@@ -796,24 +831,37 @@ struct Best {
     }
 };
 
+// K: particles of several kinds (the pair's D2 from the per-kind-pair table,
+// staged in LDS with each record's kind); otherwise the box's D2.
+template <bool K>
 struct PolF64 {
     static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
     static constexpr bool kScreen = false;
+    static constexpr bool kKinds = K;
     static constexpr int kFlushBatch = 2;
     static constexpr bool kFlushSkipEmpty = true;
     static constexpr int kWaves = 6;      // waves per SIMD the half search is compiled for
     struct Lds {
         P64 rec[W];
+        uint8_t kind[K ? W : 1];
+        double d2[K ? kMaxKinds * kMaxKinds : 1];
     };
     struct Own {
         P64 me;
+        uint32_t row;   // K: kMaxKinds * own kind
     };
     using Group = NoGroup;
     __device__ static void begin_group(const Plan&, const BoxDev&, Own&, Group&, int, int, int, int, int, uint32_t,
                                        bool) {}
+    // per-group LDS tables, written before the group's first staging barrier
+    __device__ static void group_lds(Lds& l, const Plan& p, uint32_t, int lane)
+    {
+        if (K) l.d2[lane] = p.sp_D2[lane];
+    }
     __device__ static void load_own(const Plan& p, uint32_t i, Own& o, double& x, double& y, double& z)
     {
         o.me = p.B[i];
+        o.row = K ? (uint32_t)p.spB[i] * (uint32_t)kMaxKinds : 0u;
         x = o.me.x; y = o.me.y; z = o.me.z;
     }
     __device__ static P64 self64(const Plan&, uint32_t, const Own& o) { return o.me; }
@@ -821,6 +869,7 @@ struct PolF64 {
                                  int, int, int)
     {
         l.rec[t] = p.B[j];
+        if (K) l.kind[t] = p.spB[j];
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
@@ -836,7 +885,8 @@ struct PolF64 {
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            if (accept(pq, D2, dt)) f.add(p, i, c0 + (uint32_t)(rp - l.rec), wcode(wx, wy, wz));
+            const double d2 = K ? l.d2[o.row + l.kind[rp - l.rec]] : D2;
+            if (accept(pq, d2, dt)) f.add(p, i, c0 + (uint32_t)(rp - l.rec), wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: running (key, id) minimum over the acceptable pairs
@@ -853,7 +903,8 @@ struct PolF64 {
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            if (accept(pq, D2, dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
+            const double d2 = K ? l.d2[o.row + l.kind[j - c0]] : D2;
+            if (accept(pq, d2, dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
         }
     }
 };
@@ -927,8 +978,18 @@ __device__ __forceinline__ void screen_bound(double u, const double er[3], const
     t[7] = f * (g2c + 0.5 * g1 / G0);
 }
 
+// Folded D2 constant of the m3 test for the criterion's FP32 D2 (see below).
+__device__ __forceinline__ float fold_kD2(double D2_32, double tc1, double RRb)
+{
+    const double u = 0x1.0p-24;
+    return tc1 > 0.0 ? (float)((D2_32 + tc1 + 2.0 * u * (RRb + D2_32 + tc1)) * (1.0 + 2e-6)) : (float)D2_32;
+}
+
+// Returns tc1 and RRb (for fold_kD2 with other D2 values of the box).  With
+// particle kinds B.D2 is the largest pair value; every bound term grows with
+// D2, so the bounds hold for every pair of kinds.
 __device__ __forceinline__ void screen_thresholds(const BoxDev& B, const double P[3], double V, float guard,
-                                                  ScreenBounds& g)
+                                                  ScreenBounds& g, double& tc1, double& RRb)
 {
     const double u = 0x1.0p-24, u64 = 0x1.0p-53;
     const double eg = 4.0001 * u * V + 4.0 * u64 * V;
@@ -956,13 +1017,14 @@ __device__ __forceinline__ void screen_thresholds(const BoxDev& B, const double 
     // at least kD2 - D2 - u (|fl(|r|^2) - kD2| + |fl(|r|^2) - D2|), which is >= tc1
     // when kD2 (1 - u) >= D2 (1 + u) + tc1 + 2 u RRb with RRb >= fl(|r|^2).
     // Without bounds (guard 0) the constants are the criteria's own.
-    const double dt32 = (double)B.dt_32, D2_32 = (double)B.D2_32;
-    double RRb = 0.0;
+    const double dt32 = (double)B.dt_32;
+    RRb = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) RRb += (Rk[k] + er[k]) * (Rk[k] + er[k]);
     RRb *= 1.0 + 1e-5;
+    tc1 = t[5];
     g.kdt = t[3] > 0.0 ? (float)((dt32 + t[3]) * (1.0 + 2e-6)) : B.dt_32;
-    g.kD2 = t[5] > 0.0 ? (float)((D2_32 + t[5] + 2.0 * u * (RRb + D2_32 + t[5])) * (1.0 + 2e-6)) : B.D2_32;
+    g.kD2 = fold_kD2((double)B.D2_32, t[5], RRb);
 }
 
 __global__ void k_screen_bounds(Plan p)
@@ -978,27 +1040,42 @@ __global__ void k_screen_bounds(Plan p)
         P[k] = 0.5 * cells[k] * h * (1.0 + 1e-9) + 1e-12 * (fabs(B.lo[k]) + fabs(B.hi[k]) + 2.0 * B.L[k]);
     }
     const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * 0x1.0p-24);
-    screen_thresholds(B, P, V, p.guard, p.box_sb[b]);
+    double tc1, RRb;
+    screen_thresholds(B, P, V, p.guard, p.box_sb[b], tc1, RRb);
+    if (p.nspecies > 0) {
+        // the folded constant of each pair of kinds, from the pair's own D2
+        // rounded to FP32 (entries of absent kinds are never read)
+        float* tab = p.box_kD2 + (size_t)b * (kMaxKinds * kMaxKinds);
+        for (int e = 0; e < kMaxKinds * kMaxKinds; ++e)
+            tab[e] = fold_kD2((double)(float)p.sp_D2[e], tc1, RRb);
+    }
 }
 
 
 struct alignas(16) Rec32 {
-    float4 a;   // x, y, z relative to the group centre; vx
-    float2 b;   // vy, vz
-    float2 pad;
+    float4 a;       // x, y, z relative to the group centre; vx
+    float2 b;       // vy, vz
+    uint32_t kind;  // the candidate's kind (particle kinds only)
+    uint32_t pad;
 };
 
+// K: particles of several kinds (the screen's folded D2 constant of each
+// pair of kinds from a per-box table in LDS); otherwise the box's constant.
+template <bool K>
 struct PolF32 {
     static constexpr int W = 160;         // staged records per chunk (5 KiB)
     static constexpr bool kScreen = true;
+    static constexpr bool kKinds = K;
     static constexpr int kFlushBatch = 1;
     static constexpr bool kFlushSkipEmpty = false;
     static constexpr int kWaves = 6;
     struct Lds {
         Rec32 r[W];
+        float kd2[K ? kMaxKinds * kMaxKinds : 1];
     };
     struct Own {
         float x, y, z, vx, vy, vz;   // position relative to the current group's centre
+        uint32_t row;                // K: kMaxKinds * own kind
     };
     using Group = ScreenGroup;
     __device__ static P64 self64(const Plan& p, uint32_t i, const Own&) { return p.B[i]; }
@@ -1006,7 +1083,13 @@ struct PolF32 {
     {
         const P64 m = p.B[i];
         o.vx = (float)m.vx; o.vy = (float)m.vy; o.vz = (float)m.vz;
+        o.row = K ? (uint32_t)p.spB[i] * (uint32_t)kMaxKinds : 0u;
         x = m.x; y = m.y; z = m.z;
+    }
+    // per-group LDS tables, written before the group's first staging barrier
+    __device__ static void group_lds(Lds& l, const Plan& p, uint32_t gb, int lane)
+    {
+        if (K) l.kd2[lane] = p.box_kD2[(size_t)gb * (kMaxKinds * kMaxKinds) + (uint32_t)lane];
     }
     // Centre and thresholds of the group whose cells are x in [cxf, cxl] of
     // row (gcy, gcz); its neighbourhood spans cells cxf-1..cxl+1, gcy-1..gcy+1,
@@ -1044,6 +1127,7 @@ struct PolF32 {
         l.r[t].a = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
                                (float)((q.z + sz) - g.X0[2]), (float)q.vx);
         l.r[t].b = make_float2((float)q.vy, (float)q.vz);
+        if (K) l.r[t].kind = p.spB[j];
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
@@ -1063,9 +1147,10 @@ struct PolF32 {
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const float kd = K ? l.kd2[o.row + rp->kind] : kD2;
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
-            const float m3 = fmaf(rr - kD2, g2, -(b * b));
+            const float m3 = fmaf(rr - kd, g2, -(b * b));
             if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0)) f.add(p, i, c0 + (uint32_t)(rp - l.r), wcode(wx, wy, wz));
         }
     }
@@ -1085,9 +1170,11 @@ struct PolF32 {
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const uint32_t kj = K ? l.r[j - c0].kind : 0u;
+            const float kd = K ? l.kd2[o.row + kj] : kD2;
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
-            const float m3 = fmaf(rr - kD2, g2, -(b * b));
+            const float m3 = fmaf(rr - kd, g2, -(b * b));
             if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i)) {
                 const P64 me = p.B[i], q = p.B[j];
                 double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
@@ -1098,7 +1185,7 @@ struct PolF32 {
                 }
                 const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
                 best.screened += 1u;
-                if (accept(pq, B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
+                if (accept(pq, K ? p.sp_D2[o.row + kj] : B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
             }
         }
     }
@@ -1119,7 +1206,7 @@ void k_search_half(Plan p)
     const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
-    typename Pol::Own own;
+    typename Pol::Own own{};
     if (alive) {
         bidx = p.boxidx ? p.boxidx[i] : 0u;
         const BoxDev& B = p.boxes[bidx];
@@ -1150,6 +1237,7 @@ void k_search_half(Plan p)
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
         Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
+        Pol::group_lds(lds, p, gb, lane);
         // Cells [ca, cb] of a row seen with image shift (wx, wy, wz); each lane
         // tests the sub-range [ls, le) of it (empty when ls >= le).
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz, int dy,
@@ -1203,7 +1291,7 @@ void k_search_half(Plan p)
             }
         }
     }
-    uint64_t c = valid ? found.template flush<Pol::kFlushBatch, Pol::kFlushSkipEmpty>(p, i, Pol::self64(p, i, own),
+    uint64_t c = valid ? found.template flush<Pol::kFlushBatch, Pol::kFlushSkipEmpty, Pol::kKinds>(p, i, Pol::self64(p, i, own),
                                                                                        p.boxes[bidx])
                        : 0u;
     // statistics: pairs the search kept, counted at both particles
@@ -1230,7 +1318,7 @@ void k_search_full(Plan p)
     const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
-    typename Pol::Own own;
+    typename Pol::Own own{};
     if (alive) {
         bidx = p.boxidx ? p.boxidx[i] : 0u;
         const BoxDev& B = p.boxes[bidx];
@@ -1262,6 +1350,7 @@ void k_search_full(Plan p)
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
         Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
+        Pol::group_lds(lds, p, gb, lane);
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz, int dy,
                         int dz) {
             const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];
@@ -1323,7 +1412,7 @@ __global__ void k_distribute_overflow(Plan p)
         const uint2 e = p.ovf[k];
         const P64 me = p.B[e.x];
         double key;
-        if (exact_key(p, box_of(p, e.x), me, e.y, key)) {
+        if (exact_key(p, box_of(p, e.x), e.x, me, e.y, key)) {
             post_candidate(p, e.x, e.y, key);
             post_candidate(p, e.y, e.x, key);
         }
@@ -1393,7 +1482,8 @@ __device__ int32_t search_one64_wave(const Plan& p, uint32_t i)
     const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
     const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
     const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
-    const double D2 = B.D2, dt = B.dt;
+    const double dt = B.dt;
+    const uint32_t row = kind_row(p, i);
     double best_key = __builtin_inf();
     uint32_t best_id = 0xFFFFFFFFu;
     int32_t best = -1;
@@ -1405,7 +1495,7 @@ __device__ int32_t search_one64_wave(const Plan& p, uint32_t i)
             double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
             if (shift) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-            if (accept(pq, D2, dt)) {
+            if (accept(pq, pair_D2(p, B, row, j), dt)) {
                 const double key = pq.c2 / pq.g2;
                 const uint32_t idj = p.idB[j];
                 if (key < best_key || (key == best_key && idj < best_id)) {
@@ -1494,6 +1584,8 @@ __device__ __forceinline__ void apply_bc(const BoxDev& B, double x[3], double v[
     }
 }
 
+// K: particles of several kinds (masses from the kind table).
+template <bool K>
 __global__ __launch_bounds__(1024) void k_resolve(Plan p)
 {
     __shared__ uint64_t lds[32];
@@ -1536,12 +1628,30 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
             const double tstar = (-pq.b) / pq.g2;
             double nh[3];
             direction(p.seed, p.ctl->step, ida, nh, p.dims);
-            const double hg = 0.5 * sqrt(pq.g2);
+            // masses of a and b (particle kinds), equal otherwise
+            double ma = 1.0, mb = 1.0;
+            if (K) {
+                const uint32_t ki = p.spB[i], kq = p.spB[q];
+                ma = p.sp_mass[me_a ? ki : kq];
+                mb = p.sp_mass[me_a ? kq : ki];
+            }
             double vn[3];
+            if (ma == mb) {
+                const double hg = 0.5 * sqrt(pq.g2);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double vcm = 0.5 * (va[k] + vb[k]);
-                vn[k] = me_a ? vcm + hg * nh[k] : vcm - hg * nh[k];
+                for (int k = 0; k < 3; ++k) {
+                    const double vcm = 0.5 * (va[k] + vb[k]);
+                    vn[k] = me_a ? vcm + hg * nh[k] : vcm - hg * nh[k];
+                }
+            } else {
+                // centre-of-mass velocity, |g| shared in inverse proportion to the masses
+                const double M = ma + mb, gm = sqrt(pq.g2);
+                const double wa = (mb / M) * gm, wb = (ma / M) * gm;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double vcm = fma(ma, va[k], mb * vb[k]) / M;
+                    vn[k] = me_a ? vcm + wa * nh[k] : vcm - wb * nh[k];
+                }
             }
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
@@ -1581,6 +1691,7 @@ __global__ __launch_bounds__(1024) void k_resolve(Plan p)
             __builtin_nontemporal_store(v[k], p.A + (3 + k) * N + i);
         }
         __builtin_nontemporal_store(id, p.idA + i);
+        if (K) p.spA[i] = p.spB[i];
         nx = x[0]; ny = x[1]; nz = x[2];
     }
     // a1 of the next step: cell and slot of the new position
@@ -1642,13 +1753,14 @@ inline uint32_t blocks_for(uint32_t n, uint32_t b) { return (n + b - 1) / b; }
 // Launchers
 // --------------------------------------------------------------------------
 
-hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s)
+hipError_t launch_init(const Plan& p, const double* d_state, const uint8_t* d_kind, hipStream_t s)
 {
     const uint32_t b = 256;
-    if (p.N > 0) k_init_particles<<<blocks_for(p.N, b), b, 0, s>>>(p, d_state);
+    if (p.N > 0) k_init_particles<<<blocks_for(p.N, b), b, 0, s>>>(p, d_state, d_kind);
     k_fill_u32<<<blocks_for(p.C, b) < 4096 ? blocks_for(p.C, b) : 4096, b, 0, s>>>(p.count, p.C, 0u);
     if (p.N > 0) k_fill_u32<<<4096, b, 0, s>>>(p.sl_cnt, (size_t)p.N, 0u);
     k_init_ctl<<<1, 64, 0, s>>>(p, 0);
+    if (p.N > 0 && p.nspecies > 0) k_check_kinds<<<blocks_for(p.N, b), b, 0, s>>>(p, d_kind);
     if (p.N > 0) k_bin<<<blocks_for(p.N, b), b, 0, s>>>(p);
     return hipGetLastError();
 }
@@ -1678,12 +1790,23 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     if (ev) (void)hipEventRecord(ev[KMC_PHASE_COUNT + 1], s);   // search kernel alone
     const bool full = p.search_mode == KMC_SEARCH_FULL;
     if (p.N > 0) {
+        const bool f32 = p.precision == KMC_FP32_SCREEN, kinds = p.nspecies > 0;
         if (full) {
-            if (p.precision == KMC_FP32_SCREEN) k_search_full<PolF32><<<gW, 64, 0, s>>>(p);
-            else k_search_full<PolF64><<<gW, 64, 0, s>>>(p);
+            if (f32) {
+                if (kinds) k_search_full<PolF32<true>><<<gW, 64, 0, s>>>(p);
+                else k_search_full<PolF32<false>><<<gW, 64, 0, s>>>(p);
+            } else {
+                if (kinds) k_search_full<PolF64<true>><<<gW, 64, 0, s>>>(p);
+                else k_search_full<PolF64<false>><<<gW, 64, 0, s>>>(p);
+            }
         } else {
-            if (p.precision == KMC_FP32_SCREEN) k_search_half<PolF32><<<gW, 64, 0, s>>>(p);
-            else k_search_half<PolF64><<<gW, 64, 0, s>>>(p);
+            if (f32) {
+                if (kinds) k_search_half<PolF32<true>><<<gW, 64, 0, s>>>(p);
+                else k_search_half<PolF32<false>><<<gW, 64, 0, s>>>(p);
+            } else {
+                if (kinds) k_search_half<PolF64<true>><<<gW, 64, 0, s>>>(p);
+                else k_search_half<PolF64<false>><<<gW, 64, 0, s>>>(p);
+            }
         }
     }
     mark(KMC_PHASE_FINISH);
@@ -1697,7 +1820,10 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         k_fallback64<<<512, 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RESOLVE);
-    if (p.N > 0) k_resolve<<<gN, b, 0, s>>>(p);
+    if (p.N > 0) {
+        if (p.nspecies > 0) k_resolve<true><<<gN, b, 0, s>>>(p);
+        else k_resolve<false><<<gN, b, 0, s>>>(p);
+    }
     k_advance<<<1, 64, 0, s>>>(p);
     mark(KMC_PHASE_COUNT);
     return hipGetLastError();

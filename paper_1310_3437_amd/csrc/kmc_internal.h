@@ -18,9 +18,13 @@ constexpr int kHistLanes = 64;
 // Candidates the search records per particle before the particle falls
 // back to a full search.
 constexpr int kSlots = 8;
+// Table stride of the per-kind-pair tables (= KMC_MAX_SPECIES).
+constexpr int kMaxKinds = 8;
 
 // Device copy of one box.  All derived scalars are computed once on the host
-// (L = hi - lo, R2 = R*R) so that every kernel sees the same bits.
+// (L = hi - lo, R2 = R*R) so that every kernel sees the same bits.  With
+// particle kinds D2 is the largest pair value (the screen's bounds and the
+// cell-size check use it); the criterion takes the pair's own value.
 struct alignas(16) BoxDev {
     double lo[3], hi[3], L[3], inv_h[3];
     double D2, dt, R, R2;
@@ -128,13 +132,21 @@ struct Plan {
     int32_t search_mode;           // kmc_search_mode
     int32_t dims;                  // 3, or 2 for the planar mode
     double dt_factor;              // adaptive dt: C in dt = min(cap, C dx / v_max)
+    // particle kinds (nspecies == 0: one kind, the box's D2, equal masses)
+    int32_t nspecies;
+    uint8_t* spA;                  // per particle in A order: its kind
+    uint8_t* spB;                  // per sorted particle: its kind
+    const double* sp_D2;           // [kMaxKinds][kMaxKinds]: (radius_s + radius_t)^2
+    const double* sp_mass;         // [kMaxKinds]
+    float* box_kD2;                // per box [kMaxKinds][kMaxKinds]: the FP32 screen's folded
+                                   // D2 constant of each pair of kinds this step
 };
 
 // Kernel launchers (kmc_device.hip).  `ev`, when not null, points to
 // KMC_PHASE_COUNT + 2 events recorded on `s`: ev[k] at the start of phase k,
 // ev[KMC_PHASE_COUNT] at the end of the step and ev[KMC_PHASE_COUNT + 1]
 // right before the search kernel itself (after the screen's bound kernels).
-hipError_t launch_init(const Plan& p, const double* d_state, hipStream_t s);
+hipError_t launch_init(const Plan& p, const double* d_state, const uint8_t* d_kind, hipStream_t s);
 hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev);
 hipError_t launch_read_partners(const Plan& p, int32_t* out, hipStream_t s);
 hipError_t launch_read_state(const Plan& p, double* out, hipStream_t s);

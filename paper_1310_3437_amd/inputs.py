@@ -73,6 +73,9 @@ class Workload:
     dt_rule: int = 0             # 0: fixed dt per box, 1: adaptive (box dt is the cap)
     dt_factor: float = 1.0       # adaptive rule: factor C in dt = C dx / v_max
     dims: int = 3                # 2: planar mode (one cell along z, z and vz fixed)
+    species: np.ndarray = None   # (N,) uint8 kind of each particle (id order), None: one kind
+    radius: tuple = ()           # per kind: effective radius (a pair interacts below the sum)
+    mass: tuple = ()             # per kind: mass
     info: dict = field(default_factory=dict)
 
     @property
@@ -296,10 +299,41 @@ def ppc_sweep_case(n=100_000_000, ppc=3.0, speed=1.0, ic_seed=6, seed=1, state=N
     return w
 
 
+def c6_mixture(n=10_000_000, radius=(0.5, 1.0, 1.5), mass=(1.0, 4.0, 9.0), frac=(0.5, 0.3, 0.2), periodic=True,
+               ic_seed=7, steps=10, seed=1):
+    """Three kinds of particle in a unit cube (Section 1: every particle
+    carries its own mass and effective radius).  Kind k has effective radius
+    r0 * radius[k] and mass mass[k], and makes up the fraction frac[k] of the
+    particles (each particle's kind drawn independently); positions uniform;
+    Maxwellian velocities at one temperature (sigma_v = 1 / sqrt(mass[k])).
+    r0 makes the largest pair diameter 2 r0 max(radius) equal to (3/n)^(1/3)
+    (about three particles per cell on the finest admissible grid), the cell
+    edge is the first >= that diameter, and dt = 0.2 h / <|v|> of the
+    lightest kind.  The box D2 is the largest pair value."""
+    rng = np.random.default_rng(ic_seed)
+    kind = rng.choice(len(radius), size=n, p=np.asarray(frac, dtype=np.float64) / sum(frac)).astype(np.uint8)
+    s = np.empty((6, n), dtype=np.float64)
+    s[0:3] = rng.random((3, n))
+    sig = 1.0 / np.sqrt(np.asarray(mass, dtype=np.float64))
+    s[3:6] = rng.standard_normal((3, n)) * sig[kind]
+    Dmax = (3.0 / n) ** (1.0 / 3.0)
+    r0 = Dmax / (2.0 * max(radius))
+    rad = tuple(r0 * r for r in radius)
+    Dm = 2.0 * max(rad)
+    nc = _ncell_for(1.0, Dm)
+    h = 1.0 / nc
+    dt = 0.2 * h / (MEAN_SPEED_PER_SIGMA * float(sig.max()))
+    box = Box(n=n, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), ncell=(nc, nc, nc), periodic=(periodic,) * 3,
+              D2=Dm * Dm, dt=dt)
+    return Workload("c6_mixture", [box], s, steps, seed=seed, species=kind, radius=rad,
+                    mass=tuple(float(m) for m in mass), info=dict(radius=rad, frac=frac, h=h))
+
+
 CONFIGS = {
     "c1_small": c1_small,
     "c2_shock": c2_shock,
     "c3_sphere": c3_sphere,
     "c4_batch": c4_batch,
     "c5_blobs": c5_blobs,
+    "c6_mixture": c6_mixture,
 }

@@ -42,6 +42,19 @@ class KmcBox(C.Structure):
     ]
 
 
+KMC_MAX_SPECIES = 8
+
+
+class KmcSpecies(C.Structure):
+    _fields_ = [
+        ("count", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("radius", C.c_double * KMC_MAX_SPECIES),
+        ("mass", C.c_double * KMC_MAX_SPECIES),
+        ("d_kind", C.c_void_p),
+    ]
+
+
 class KmcConfig(C.Structure):
     _fields_ = [
         ("seed", C.c_uint64),
@@ -59,6 +72,7 @@ class KmcConfig(C.Structure):
         ("reserved", C.c_int32 * 2),
         ("guard_scale", C.c_double),
         ("dt_factor", C.c_double),
+        ("species", C.POINTER(KmcSpecies)),
     ]
 
 
@@ -166,10 +180,29 @@ def make_boxes(boxes):
     return arr
 
 
+def make_species(radius, mass, d_kind_ptr=0):
+    """kmc_species for kinds with the given effective radii and masses; the
+    per-particle kinds live at device address d_kind_ptr (uint8, id order)."""
+    sp = KmcSpecies()
+    if not 1 <= len(radius) <= KMC_MAX_SPECIES or len(mass) != len(radius):
+        raise ValueError("1..8 kinds, one radius and one mass each")
+    sp.count = len(radius)
+    for k in range(len(radius)):
+        sp.radius[k] = float(radius[k])
+        sp.mass[k] = float(mass[k])
+    sp.d_kind = int(d_kind_ptr)
+    return sp
+
+
 def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR, history=0,
                 recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0,
-                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF, dims=3):
+                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF, dims=3, species=None):
+    """kmc_config from keyword arguments; species: a KmcSpecies (kept alive
+    with the returned structure) or None for one kind of particle."""
     c = KmcConfig()
+    if species is not None:
+        c.species = C.pointer(species)
+        c._species = species
     c.seed = int(seed) & ((1 << 64) - 1)
     c.step0 = int(step0)
     c.precision = int(precision)
@@ -207,9 +240,11 @@ def box_with_kappa(box, kappa):
 def _tune_key(boxes, device_name, flags, steps, config):
     import hashlib
     import json
+    sp = config.get("species")
     desc = dict(device=device_name, flags=int(flags), steps=int(steps),
+                species=None if sp is None else [list(sp.radius)[:sp.count], list(sp.mass)[:sp.count]],
                 config={k: config[k] for k in sorted(config) if k not in ("seed", "step0", "history", "profile",
-                                                                          "use_graph")},
+                                                                          "use_graph", "species")},
                 boxes=[dict(n=int(b.n), lo=list(map(float, b.lo)), hi=list(map(float, b.hi)),
                             ncell=list(map(int, b.ncell)), periodic=list(map(bool, b.periodic)),
                             sphere=bool(b.sphere), R=float(b.R), D2=float(b.D2), dt=float(b.dt)) for b in boxes])
@@ -285,12 +320,24 @@ class Sim:
     kmc_init: x, y, z, vx, vy, vz rows, boxes concatenated in order.
     """
 
-    def __init__(self, boxes, state, device="cuda", **config):
+    def __init__(self, boxes, state, device="cuda", kinds=None, **config):
+        """kinds: None (one kind of particle) or (kind, radius, mass): the kind
+        of each particle (N integers, id order) and each kind's effective
+        radius and mass."""
         import torch
         self._torch = torch
         L = load()
         self.boxes = list(boxes)
         self.device = torch.device(device)
+        if kinds is not None:
+            kind, radius, mass = kinds
+            kind = np.asarray(kind)
+            if kind.shape != (sum(int(b.n) for b in self.boxes),):
+                raise ValueError("kinds: one kind per particle")
+            if kind.size and (int(kind.min()) < 0 or int(kind.max()) > 255):
+                raise ValueError("kinds: values must fit in a byte (the library checks them against the count)")
+            self._kind = torch.as_tensor(kind, dtype=torch.uint8).to(self.device).contiguous()
+            config = dict(config, species=make_species(radius, mass, self._kind.data_ptr()))
         self.config = make_config(**config)
         self._boxarr = make_boxes(self.boxes)
         st = torch.as_tensor(state, dtype=torch.float64).to(self.device).contiguous()
@@ -307,6 +354,7 @@ class Sim:
                "kmc_init")
         self._ctx = ctx
         torch.cuda.current_stream(self.device).synchronize()
+        self._kind = None   # read by kmc_init only
 
     def _stream(self):
         return C.c_void_p(self._torch.cuda.current_stream(self.device).cuda_stream)

@@ -26,14 +26,16 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(kmc.EXPORTS)
-    assert L.kmc_abi_version() == 2
+    assert L.kmc_abi_version() == 3
 
 
 def test_struct_sizes_match_header():
-    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes
+    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes and the
+    # species pointer; kmc_species: two u32, 2 x 8 doubles, a pointer
     assert C.sizeof(kmc.KmcBox) == 128
-    assert C.sizeof(kmc.KmcConfig) == 80
+    assert C.sizeof(kmc.KmcConfig) == 88
     assert C.sizeof(kmc.KmcStats) == 136
+    assert C.sizeof(kmc.KmcSpecies) == 144
 
 
 def _ws(boxes, **cfg):
@@ -146,3 +148,27 @@ def test_absorbing_faces_accepted_and_one_extra_cell_per_box():
     b.absorb = (True, False, False)
     rc, n1 = _ws([b])
     assert rc == 0
+
+
+def _species(count=2, radius=(0.05, 0.1), mass=(1.0, 2.0), reserved=0):
+    sp = kmc.KmcSpecies()
+    sp.count = count
+    sp.reserved = reserved
+    for k in range(len(radius)):
+        sp.radius[k] = radius[k]
+    for k in range(len(mass)):
+        sp.mass[k] = mass[k]
+    return sp
+
+
+def test_species_workspace_and_validation():
+    rc, n0 = _ws([_good()])
+    rc, n1 = _ws([_good()], species=_species())
+    assert rc == 0 and n1 >= n0 + 2 * 100     # two kind arrays of one byte per particle
+    for bad in [_species(count=0), _species(count=9), _species(reserved=1),
+                _species(radius=(0.05, 0.0)), _species(radius=(0.05, float("nan"))),
+                _species(mass=(1.0, -2.0)), _species(mass=(float("inf"), 1.0)),
+                _species(radius=(0.05, 0.13))]:          # largest pair 0.26 > cell edge 0.25
+        assert _ws([_good()], species=bad)[0] == kmc.KMC_EINVAL
+    # the box's own D2 is still validated, the pair table decides the cell check
+    assert _ws([_good()], species=_species(radius=(0.05, 0.125)))[0] == 0

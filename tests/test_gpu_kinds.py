@@ -1,0 +1,150 @@
+"""GPU parity with particles of several kinds (effective radius and mass per
+kind).  The pair criterion takes (radius_s + radius_t)^2 in place of the box
+D2 and colliding pairs of unequal masses scatter with the mass-weighted
+centre-of-mass formula; partners, per-step (npairs, digest) and the state
+must equal the CPU oracle's exactly, in both precisions and both search
+organisations, on a random three-kind mixture, with reflecting walls, on
+pairs placed at the FP32 screen's decision boundaries, and at N = 1e6."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1310_3437_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _prec(kmc, name):
+    return kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
+
+
+def _kinds(w):
+    return (w.species, w.radius, w.mass)
+
+
+def run_kinds(kmc, w, steps, precision, **cfg):
+    print(f"\n[kinds] {w.name} N={w.n} steps={steps} {precision} cfg={cfg}", flush=True)
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics,
+                  precision=_prec(kmc, precision), kinds=_kinds(w), **cfg)
+    ref = O.Run(w)
+    hist = []
+    for s in range(steps):
+        sim.step(1)
+        hist.append(ref.step())
+        p = sim.partners().cpu().numpy()
+        bad = np.flatnonzero(p != ref.partner_by_id)
+        assert bad.size == 0, f"step {s}: {bad.size} partner mismatches, first ids {bad[:5]}"
+    hn, hd = sim.history()
+    assert [(int(a), int(b)) for a, b in zip(hn, hd)][-steps:] == hist
+    assert np.array_equal(sim.state().cpu().numpy(), ref.full_state()), "states differ"
+    stats = sim.stats()
+    sim.close()
+    print(f"[kinds] ok, pairs per step {[h[0] for h in hist]}", flush=True)
+    return hist, stats
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mixture_matches_oracle(kmc, precision, mode):
+    w = I.c6_mixture(n=8192, steps=4)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    hist, _ = run_kinds(kmc, w, 4, precision, search_mode=sm)
+    assert min(h[0] for h in hist) > 300
+
+
+def test_mixture_reflecting_walls(kmc):
+    w = I.c6_mixture(n=6000, periodic=False, ic_seed=8, steps=3)
+    run_kinds(kmc, w, 3, "fp32")
+
+
+def test_mixture_graph_replay(kmc):
+    w = I.c6_mixture(n=5000, ic_seed=9, steps=3)
+    run_kinds(kmc, w, 3, "fp32", use_graph=True)
+
+
+def test_one_kind_table_equals_no_kinds(kmc):
+    """A single kind of radius D/2 reproduces the gas without kinds."""
+    w = I.c1_small(steps=3)
+    D = w.info["D"]
+    a = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=kmc.KMC_FP32_SCREEN)
+    b = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=kmc.KMC_FP32_SCREEN,
+                kinds=(np.zeros(w.n, np.uint8), (D / 2,), (3.0,)))
+    a.step(3)
+    b.step(3)
+    ha, hb = a.history(), b.history()
+    assert np.array_equal(ha[0], hb[0]) and np.array_equal(ha[1], hb[1]) and int(ha[0].sum()) > 100
+    assert bool((a.state() == b.state()).all().item())
+    a.close()
+    b.close()
+
+
+def test_invalid_kind_is_rejected(kmc):
+    w = I.c6_mixture(n=1000, steps=1)
+    sp = w.species.copy()
+    sp[517] = 3            # three kinds: 0, 1, 2
+    with pytest.raises(kmc.KmcError):
+        kmc.Sim(w.boxes, w.state, device="cuda:0", kinds=(sp, w.radius, w.mass))
+
+
+def adversarial_kinds(seed=0, bulk=0.0):
+    """Isolated pairs of random kinds placed 2^-18 .. 2^-50 relative from the
+    boundaries of their own pair diameter (radius_s + radius_t), of t* = dt
+    and of t* = 0, one pair per cell on a 3-spaced lattice of a periodic
+    30^3 grid."""
+    rng = np.random.default_rng(seed)
+    nc, L = 30, 1.0
+    h = L / nc
+    radius = (0.15 * h, 0.3 * h, 0.45 * h)      # largest pair diameter 0.9 h
+    mass = (1.0, 2.0, 5.0)
+    dt = 0.01
+    pts, kinds = [], []
+    for a in range(10):
+        for b in range(10):
+            for c in range(10):
+                ctr = (np.array([3 * a + 1, 3 * b + 1, 3 * c + 1]) + 0.5) * h
+                ka, kb = rng.integers(3), rng.integers(3)
+                D = radius[ka] + radius[kb]
+                kind = ("radius", "tend", "tzero")[rng.integers(3)]
+                gdir = rng.standard_normal(3)
+                gdir /= np.linalg.norm(gdir)
+                perp = np.cross(gdir, rng.standard_normal(3))
+                perp /= np.linalg.norm(perp)
+                gmag = rng.uniform(0.5, 2.0)
+                eps = 2.0 ** -rng.integers(18, 51) * (1 if rng.random() < 0.5 else -1)
+                if kind == "radius":
+                    t0, d = rng.uniform(0.2, 0.8) * dt, D * (1 + eps)
+                elif kind == "tend":
+                    t0, d = dt * (1 + eps), D * rng.uniform(0.1, 0.9)
+                else:
+                    t0, d = eps * dt, D * rng.uniform(0.1, 0.9)
+                g = gdir * gmag
+                r = -g * t0 + perp * d
+                V0 = rng.standard_normal(3) * bulk
+                pts += [(ctr - r / 2, V0 - g / 2), (ctr + r / 2, V0 + g / 2)]
+                kinds += [ka, kb]
+    n = len(pts)
+    s = np.empty((6, n))
+    for k, (x, v) in enumerate(pts):
+        s[0:3, k] = x
+        s[3:6, k] = v
+    s[0:3] = np.mod(s[0:3], L)
+    box = I.Box(n=n, lo=(0.0,) * 3, hi=(L,) * 3, ncell=(nc,) * 3, periodic=(True,) * 3, D2=(0.9 * h) ** 2, dt=dt)
+    perm = rng.permutation(n)
+    return I.Workload("adversarial_kinds", [box], s[:, perm].copy(), 2, species=np.array(kinds, np.uint8)[perm],
+                      radius=radius, mass=mass)
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("bulk", [0.0, 20.0])
+def test_screen_exact_on_adversarial_kinds(kmc, bulk, mode):
+    w = adversarial_kinds(seed=21, bulk=bulk)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    _, s64 = run_kinds(kmc, w, 2, "fp64", search_mode=sm)
+    _, s32 = run_kinds(kmc, w, 2, "fp32", search_mode=sm)
+    assert s32["candidates"] >= s64["candidates"]
+
+
+@pytest.mark.timeout(600)
+def test_mixture_1e6_matches_oracle(kmc):
+    w = I.c6_mixture(n=1_000_000, steps=2)
+    run_kinds(kmc, w, 2, "fp32")

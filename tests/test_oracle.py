@@ -705,3 +705,134 @@ def test_absorbing_axes_are_validated():
         O.step_box(bad, s.copy(), np.zeros(1, np.uint32), 0, gone=np.zeros(1, np.uint8))
     with pytest.raises(ValueError):     # absorbing faces need the gone flags
         O.step_box(_abs_box(1), s.copy(), np.zeros(1, np.uint32), 0)
+
+
+# --------------------------------------------------------------------------
+# Kinds of particles (Section 1: each particle carries a mass and an
+# effective radius; candidates must be within each other's effective radii)
+# --------------------------------------------------------------------------
+
+def _kinds_box(n, dt=0.01):
+    return I.Box(n=n, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(4, 4, 4), periodic=(True,) * 3, D2=1e-4, dt=dt)
+
+
+def _approach(d):
+    """Particle 0 at rest at the centre; particle 1 passes it along -x with
+    impact parameter d: closest approach |d| at t* = 2^-8 (g2 = 1)."""
+    s = np.zeros((6, 2))
+    s[0:3, 0] = 0.5
+    s[0:3, 1] = (0.5 + 2.0 ** -8, 0.5 + d, 0.5)
+    s[3, 1] = -1.0
+    return s
+
+
+@pytest.mark.parametrize("kinds,d,accepted", [
+    ((0, 1), 0.039, True),    # below 0.01 + 0.03 (but above 2 x 0.01)
+    ((0, 1), 0.041, False),   # above 0.01 + 0.03 (but below 2 x 0.03)
+    ((0, 0), 0.019, True),
+    ((0, 0), 0.021, False),
+    ((1, 1), 0.059, True),
+    ((1, 1), 0.061, False),
+    ((1, 0), 0.039, True),
+])
+def test_effective_radii_add(kinds, d, accepted):
+    s = _approach(d)
+    sp = np.array(kinds, np.uint8)
+    p, _ = O.find_partners(_kinds_box(2), s, kinds=(sp, (0.01, 0.03), (1.0, 1.0)))
+    assert list(p) == ([1, 0] if accepted else [-1, -1])
+    pb, _ = O.find_partners(_kinds_box(2), s, brute=True, kinds=(sp, (0.01, 0.03), (1.0, 1.0)))
+    assert list(pb) == list(p)
+
+
+def test_one_kind_table_reproduces_the_plain_step():
+    """A single kind of radius D/2 and any mass is the gas without kinds:
+    (D/2 + D/2)^2 is D*D exactly and equal masses take the same formula."""
+    w = I.c1_small()
+    D = w.info["D"]
+    box = w.boxes[0]
+    assert box.D2 == D * D
+    a = np.ascontiguousarray(w.state.copy())
+    b = np.ascontiguousarray(w.state.copy())
+    ids = np.arange(w.n, dtype=np.uint32)
+    kinds = (np.zeros(w.n, np.uint8), (D / 2,), (2.5,))
+    for step in range(3):
+        ra = O.step_box(box, a, ids, step, seed=w.seed)
+        rb = O.step_box(box, b, ids, step, seed=w.seed, kinds=kinds)
+        assert np.array_equal(ra[0], rb[0]) and ra[1:] == rb[1:]
+        assert ra[1] > 50
+    assert np.array_equal(a, b)
+
+
+def _unequal_pair(ma, mc):
+    s = _approach(0.02)
+    s[3:6, 0] = (0.25, -0.5, 0.125)     # a moving frame: nothing cancels
+    s[3:6, 1] += (0.25, -0.5, 0.125)
+    kinds = (np.array([0, 1], np.uint8), (0.02, 0.02), (ma, mc))
+    return s, kinds
+
+
+@pytest.mark.parametrize("ma,mc", [(1.0, 3.0), (7.0, 0.5), (1.0, 1.0)])
+def test_unequal_masses_keep_momentum_energy_and_relative_speed(ma, mc):
+    s, kinds = _unequal_pair(ma, mc)
+    pre = s.copy()
+    ids = np.array([0, 1], np.uint32)
+    p, npairs, _, _ = O.step_box(_kinds_box(2), s, ids, 5, seed=3, kinds=kinds, kinematics=1)
+    assert list(p) == [1, 0] and npairs == 1
+    va, vc = pre[3:6, 0], pre[3:6, 1]
+    wa, wc = s[3:6, 0], s[3:6, 1]
+    mom0, mom1 = ma * va + mc * vc, ma * wa + mc * wc
+    assert np.allclose(mom1, mom0, rtol=0, atol=1e-15 * (ma + mc) * 2)
+    e0 = ma * (va @ va) + mc * (vc @ vc)
+    e1 = ma * (wa @ wa) + mc * (wc @ wc)
+    assert abs(e1 - e0) <= 1e-14 * e0
+    g = np.linalg.norm(vc - va)
+    assert abs(np.linalg.norm(wc - wa) - g) <= 1e-15 * 4
+    # a (the smaller id) leaves along +n relative to c, with the CM velocity unchanged
+    n = O.direction(3, 5, 0)
+    assert np.allclose((wa - wc) / g, n, rtol=0, atol=1e-15 * 8)
+    assert np.allclose(mom1 / (ma + mc), mom0 / (ma + mc), rtol=0, atol=1e-15 * 4)
+    # the lighter particle takes the larger share of |g|
+    if ma != mc:
+        share_a = np.linalg.norm(wa - mom1 / (ma + mc)) / g
+        assert abs(share_a - mc / (ma + mc)) <= 1e-14
+
+
+def test_mixture_collisions_conserve_momentum_and_energy():
+    w = I.c6_mixture(n=6000, steps=1)
+    box = w.boxes[0]
+    s = np.ascontiguousarray(w.state.copy())
+    pre = s.copy()
+    m = np.asarray(w.mass)[w.species]
+    ids = np.arange(w.n, dtype=np.uint32)
+    p, npairs, _, _ = O.step_box(box, s, ids, 0, seed=w.seed, kinds=(w.species, w.radius, w.mass))
+    assert npairs > 200
+    mixed = 0
+    for i in range(w.n):
+        j = int(p[i])
+        if j > i and p[j] == i:
+            mixed += int(w.species[i] != w.species[j])
+            mom0 = m[i] * pre[3:6, i] + m[j] * pre[3:6, j]
+            mom1 = m[i] * s[3:6, i] + m[j] * s[3:6, j]
+            assert np.allclose(mom1, mom0, rtol=0, atol=1e-14 * (m[i] + m[j]) * np.abs(pre[3:6, [i, j]]).max())
+            e0 = m[i] * pre[3:6, i] @ pre[3:6, i] + m[j] * pre[3:6, j] @ pre[3:6, j]
+            e1 = m[i] * s[3:6, i] @ s[3:6, i] + m[j] * s[3:6, j] @ s[3:6, j]
+            assert abs(e1 - e0) <= 1e-13 * e0
+    assert mixed > 50
+
+
+def test_mixture_cell_list_equals_bruteforce():
+    w = I.c6_mixture(n=2500, steps=1)
+    kinds = (w.species, w.radius, w.mass)
+    p, _ = O.find_partners(w.boxes[0], w.state, kinds=kinds)
+    pb, _ = O.find_partners(w.boxes[0], w.state, brute=True, kinds=kinds)
+    assert np.array_equal(p, pb) and (p >= 0).sum() > 300
+
+
+def test_kinds_are_validated():
+    s = _approach(0.02)
+    for kinds in [(np.array([0, 2], np.uint8), (0.01, 0.03), (1.0, 1.0)),     # kind beyond the table
+                  (np.array([0, 1], np.uint8), (0.01, 0.0), (1.0, 1.0)),      # zero radius
+                  (np.array([0, 1], np.uint8), (0.01, 0.03), (1.0, -1.0)),    # negative mass
+                  (np.zeros(2, np.uint8), (0.01,) * 9, (1.0,) * 9)]:          # more than 8 kinds
+        with pytest.raises(ValueError):
+            O.find_partners(_kinds_box(2), s, kinds=kinds)
