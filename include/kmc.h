@@ -130,10 +130,12 @@ typedef struct kmc_box {
  *   radius[s]  effective radius of kind s (finite, > 0), s < count;
  *   mass[s]    mass of kind s (finite, > 0), s < count;
  *   d_kind     device pointer, n_total bytes in id order (box offsets as for
- *              the state): the kind of each particle, < count; read once
- *              during kmc_init (an entry >= count makes kmc_init fail with
- *              KMC_EINVAL).
- * The structure is read during kmc_workspace_bytes and kmc_init only. */
+ *              the state): the kind of each particle, < count; read on the
+ *              caller's stream during kmc_init (and during each context that
+ *              kmc_autotune creates); an entry >= count makes kmc_init fail
+ *              with KMC_EINVAL.
+ * The structure is read during kmc_workspace_bytes, kmc_init and
+ * kmc_autotune only; the context keeps a copy of count, radius and mass. */
 #define KMC_MAX_SPECIES 8
 typedef struct kmc_species {
     uint32_t count;
@@ -177,7 +179,8 @@ typedef struct kmc_config {
                                   rule), otherwise finite and > 0                         */
     const kmc_species* species; /* NULL: one kind of particle (each box's D2, equal
                                    masses); otherwise the kinds described above (host
-                                   pointer, read by kmc_workspace_bytes and kmc_init)   */
+                                   pointer, read by kmc_workspace_bytes, kmc_init and
+                                   kmc_autotune)                                        */
 } kmc_config;
 
 /* Time step rules.

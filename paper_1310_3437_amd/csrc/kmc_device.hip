@@ -613,8 +613,6 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
 // sub-range of the window from LDS.
 // --------------------------------------------------------------------------
 
-// Exact FP64 search of one particle over its full 27-cell neighbourhood,
-// straight from the sorted records (rechecks, list overflow, fallback).
 // Squared interaction diameter of the pair of sorted particles (i, j): the
 // box's D2 for one kind of particle, else (radius_s + radius_t)^2 of their
 // kinds (row = kMaxKinds * kind of i).
@@ -628,6 +626,8 @@ __device__ __forceinline__ double pair_D2(const Plan& p, const BoxDev& B, uint32
     return p.nspecies ? p.sp_D2[row_i + p.spB[j]] : B.D2;
 }
 
+// Exact FP64 search of one particle over its full 27-cell neighbourhood,
+// straight from the sorted records (rechecks, list overflow, fallback).
 __device__ int32_t search_one64(const Plan& p, uint32_t i)
 {
     if (p.idB[i] & kGone) return -1;
