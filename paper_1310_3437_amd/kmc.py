@@ -237,12 +237,11 @@ def box_with_kappa(box, kappa):
     return nb
 
 
-def _tune_key(boxes, device_name, flags, steps, config):
+def _tune_key(boxes, device_name, flags, steps, config, kinds=None):
     import hashlib
     import json
-    sp = config.get("species")
     desc = dict(device=device_name, flags=int(flags), steps=int(steps),
-                species=None if sp is None else [list(sp.radius)[:sp.count], list(sp.mass)[:sp.count]],
+                kinds=None if kinds is None else [list(map(float, kinds[1])), list(map(float, kinds[2]))],
                 config={k: config[k] for k in sorted(config) if k not in ("seed", "step0", "history", "profile",
                                                                           "use_graph", "species")},
                 boxes=[dict(n=int(b.n), lo=list(map(float, b.lo)), hi=list(map(float, b.hi)),
@@ -251,18 +250,19 @@ def _tune_key(boxes, device_name, flags, steps, config):
     return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()
 
 
-def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=None, **config):
+def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=None, kinds=None, **config):
     """Run kmc_autotune on `state`; returns (boxes, config dict, tuning dict).
-    The boxes differ from the input only with KMC_TUNE_CELLS.  With `cache`
-    (a JSON file path) a previous choice for the same device, boxes, flags
-    and configuration is reused without timing, so repeated runs make the
-    same choice."""
+    The boxes differ from the input only with KMC_TUNE_CELLS.  kinds as for
+    Sim (pass them to Sim again with the returned configuration).  With
+    `cache` (a JSON file path) a previous choice for the same device, boxes,
+    flags, kinds and configuration is reused without timing, so repeated runs
+    make the same choice."""
     import json
     import torch
     boxes = list(boxes)
     key = None
     if cache is not None:
-        key = _tune_key(boxes, torch.cuda.get_device_name(torch.device(device)), flags, steps, config)
+        key = _tune_key(boxes, torch.cuda.get_device_name(torch.device(device)), flags, steps, config, kinds)
         if os.path.exists(cache):
             with open(cache) as fh:
                 hit = json.load(fh).get(key)
@@ -271,12 +271,16 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
                 nb = [box_with_kappa(b, kappa) for b in boxes] if kappa > 0 else boxes
                 return nb, dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"]), \
                     dict(best=hit["best"], tried=hit["tried"], cached=True)
-    cfg = make_config(**config)
+    spc = {}
+    if kinds is not None:
+        kind_t = torch.as_tensor(np.asarray(kinds[0]), dtype=torch.uint8).to(device).contiguous()
+        spc = dict(species=make_species(kinds[1], kinds[2], kind_t.data_ptr()))
+    cfg = make_config(**config, **spc)
     arr = make_boxes(boxes)
     st = torch.as_tensor(state, dtype=torch.float64).to(device).contiguous()
     # the largest candidate: the finest grid (kappa = 1) and the smallest blocks
     probe = [box_with_kappa(b, 1.0) for b in boxes] if flags & KMC_TUNE_CELLS else boxes
-    need = workspace_bytes(probe, make_config(**dict(config, block_size=64)))
+    need = workspace_bytes(probe, make_config(**dict(config, block_size=64), **spc))
     ws = torch.empty(need + 256, dtype=torch.uint8, device=device)
     ptr = (ws.data_ptr() + 255) // 256 * 256
     out_b = (KmcBox * len(boxes))()

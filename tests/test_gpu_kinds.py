@@ -148,3 +148,19 @@ def test_screen_exact_on_adversarial_kinds(kmc, bulk, mode):
 def test_mixture_1e6_matches_oracle(kmc):
     w = I.c6_mixture(n=1_000_000, steps=2)
     run_kinds(kmc, w, 2, "fp32")
+
+
+def test_autotune_with_kinds(kmc):
+    """The autotuner accepts kinds; its launch and cell choice leave the
+    results equal to the oracle's on the tuned boxes."""
+    w = I.c6_mixture(n=20_000, ic_seed=10, steps=2)
+    boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0",
+                                   flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_CELLS, steps=2, kinds=_kinds(w),
+                                   seed=w.seed, precision=kmc.KMC_FP32_SCREEN)
+    best = tun["tried"][tun["best"]]
+    print(f"\n[kinds] tuned kappa {best['kappa']} grid {boxes[0].ncell} {cfg['search_mode']}/{cfg['block_size']}",
+          flush=True)
+    assert np.isfinite(best["ms_per_step"])
+    assert "species" not in cfg
+    w.boxes = boxes
+    run_kinds(kmc, w, 2, "fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
