@@ -119,6 +119,15 @@ def test_c5_blobs_scaled(kmc, precision):
     assert exact
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_long_run_graph_replay(kmc, precision):
+    """Sixty steps replayed from one captured graph (checked every ten steps):
+    lists, counters and the history ring stay exact over many steps."""
+    w = I.c1_small(n=20_000, steps=60)
+    d, exact = run_parity(kmc, w, 60, check_every=10, precision=precision, use_graph=True, history=64)
+    assert exact and min(n for n, _ in d) > 500
+
+
 def test_velocity_only_kinematics(kmc):
     w = I.c1_small(steps=3)
     w.kinematics = 1
