@@ -722,15 +722,17 @@ __device__ __forceinline__ uint32_t wcode(int wx, int wy, int wz)
 }
 
 struct Found {
-    uint32_t j[kReg];
+    uint32_t* sj; // this lane's kept indices in LDS: pair k at sj[64 k] (one store per pair
+                  // instead of a select over register slots)
     uint32_t w;   // image shift of pair k in bits 6k..6k+5: (wx+1) | (wy+1) << 2 | (wz+1) << 4
+    uint32_t sh;  // 6 n
     int n;
     __device__ __forceinline__ void add(const Plan& p, uint32_t i, uint32_t jj, uint32_t wcode)
     {
         if (n < kReg) {
-#pragma unroll
-            for (int k = 0; k < kReg; ++k) j[k] = (n == k) ? jj : j[k];
-            w |= wcode << (6 * n);
+            sj[64 * n] = jj;
+            w |= wcode << sh;
+            sh += 6u;
             ++n;
         } else {
             const uint32_t idx = atomicAdd(&p.ctl->ovf_count, 1u);
@@ -752,6 +754,9 @@ struct Found {
     __device__ __forceinline__ uint32_t flush(const Plan& p, uint32_t i, const P64& me, const BoxDev& B)
     {
         const uint32_t row = K ? kind_row(p, i) : 0u;
+        uint32_t j[kReg];
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) j[k] = k < n ? sj[64 * k] : 0u;
         double key[kReg];
         bool acc[kReg];
 #pragma unroll
@@ -878,15 +883,13 @@ struct PolF64 {
     {
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         const double D2 = B.D2, dt = B.dt;
-        const P64* rp = l.rec + (j0 - c0);
-        const P64* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
-        for (; rp < re; ++rp) {
-            const P64 q = *rp;
+        for (uint32_t j = j0; j < j1; ++j) {
+            const P64 q = l.rec[j - c0];
             double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
             if (SH) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
-            const double d2 = K ? l.d2[o.row + l.kind[rp - l.rec]] : D2;
-            if (accept(pq, d2, dt)) f.add(p, i, c0 + (uint32_t)(rp - l.rec), wcode(wx, wy, wz));
+            const double d2 = K ? l.d2[o.row + l.kind[j - c0]] : D2;
+            if (accept(pq, d2, dt)) f.add(p, i, j, wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: running (key, id) minimum over the acceptable pairs
@@ -1053,10 +1056,10 @@ __global__ void k_screen_bounds(Plan p)
 
 
 struct alignas(16) Rec32 {
-    float4 a;       // x, y, z relative to the group centre; vx
-    float2 b;       // vy, vz
-    uint32_t kind;  // the candidate's kind (particle kinds only)
-    uint32_t pad;
+    float4 a;   // x, y, z relative to the group centre; vx
+    float4 b;   // vy, vz, the candidate's kind (particle kinds only) and its sorted
+                // index (bit patterns): one 16-byte read gives the pair test and
+                // the index a kept pair records
 };
 
 // K: particles of several kinds (the screen's folded D2 constant of each
@@ -1126,8 +1129,8 @@ struct PolF32 {
                      sz = wz ? (double)wz * B.L[2] : 0.0;
         l.r[t].a = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
                                (float)((q.z + sz) - g.X0[2]), (float)q.vx);
-        l.r[t].b = make_float2((float)q.vy, (float)q.vz);
-        if (K) l.r[t].kind = p.spB[j];
+        l.r[t].b = make_float4((float)q.vy, (float)q.vz, __uint_as_float(K ? (uint32_t)p.spB[j] : 0u),
+                               __uint_as_float(j));
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
@@ -1141,17 +1144,17 @@ struct PolF32 {
         const Rec32* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
         for (; rp < re; ++rp) {
             const float4 qa = rp->a;
-            const float2 qb = rp->b;
+            const float4 qb = rp->b;
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const float kd = K ? l.kd2[o.row + rp->kind] : kD2;
+            const float kd = K ? l.kd2[o.row + __float_as_uint(qb.z)] : kD2;
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
             const float m3 = fmaf(rr - kd, g2, -(b * b));
-            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0)) f.add(p, i, c0 + (uint32_t)(rp - l.r), wcode(wx, wy, wz));
+            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0)) f.add(p, i, __float_as_uint(qb.w), wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: every pair the screen cannot reject is decided in
@@ -1164,13 +1167,13 @@ struct PolF32 {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
         for (uint32_t j = j0; j < j1; ++j) {
             const float4 qa = l.r[j - c0].a;
-            const float2 qb = l.r[j - c0].b;
+            const float4 qb = l.r[j - c0].b;
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const uint32_t kj = K ? l.r[j - c0].kind : 0u;
+            const uint32_t kj = K ? __float_as_uint(qb.z) : 0u;
             const float kd = K ? l.kd2[o.row + kj] : kD2;
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
@@ -1217,11 +1220,12 @@ void k_search_half(Plan p)
         cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
         rowkey = B.coff + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
     }
+    __shared__ uint32_t found_j[kReg * 64];
     Found found;
+    found.sj = found_j + lane;
     found.n = 0;
     found.w = 0u;
-#pragma unroll
-    for (int k = 0; k < kReg; ++k) found.j[k] = 0;
+    found.sh = 0u;
     uint64_t remaining = __ballot(alive);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
