@@ -1055,12 +1055,6 @@ __global__ void k_screen_bounds(Plan p)
 }
 
 
-struct alignas(16) Rec32 {
-    float4 a;   // x, y, z relative to the group centre; vx
-    float4 b;   // vy, vz, the candidate's kind (particle kinds only) and its sorted
-                // index (bit patterns): one 16-byte read gives the pair test and
-                // the index a kept pair records
-};
 
 // K: particles of several kinds (the screen's folded D2 constant of each
 // pair of kinds from a per-box table in LDS); otherwise the box's constant.
@@ -1072,8 +1066,14 @@ struct PolF32 {
     static constexpr int kFlushBatch = 1;
     static constexpr bool kFlushSkipEmpty = false;
     static constexpr int kWaves = 6;
+    // A staged candidate is two 16-byte halves in two arrays: a = x, y, z
+    // relative to the group centre and vx; b = vy, vz, its kind (particle
+    // kinds only) and its sorted index (bit patterns).  With 16-byte strides
+    // consecutive records fall in distinct LDS banks (a 32-byte record would
+    // use only half of them).
     struct Lds {
-        Rec32 r[W];
+        float4 a[W];
+        float4 b[W];
         float kd2[K ? kMaxKinds * kMaxKinds : 1];
     };
     struct Own {
@@ -1127,10 +1127,10 @@ struct PolF32 {
         const P64 q = p.B[j];
         const double sx = wx ? (double)wx * B.L[0] : 0.0, sy = wy ? (double)wy * B.L[1] : 0.0,
                      sz = wz ? (double)wz * B.L[2] : 0.0;
-        l.r[t].a = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
-                               (float)((q.z + sz) - g.X0[2]), (float)q.vx);
-        l.r[t].b = make_float4((float)q.vy, (float)q.vz, __uint_as_float(K ? (uint32_t)p.spB[j] : 0u),
-                               __uint_as_float(j));
+        l.a[t] = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
+                             (float)((q.z + sz) - g.X0[2]), (float)q.vx);
+        l.b[t] = make_float4((float)q.vy, (float)q.vz, __uint_as_float(K ? (uint32_t)p.spB[j] : 0u),
+                             __uint_as_float(j));
     }
     template <bool SH>
     __device__ static void scan(const Plan& p, const Lds& l, uint32_t c0, uint32_t j0, uint32_t j1, uint32_t i,
@@ -1140,11 +1140,11 @@ struct PolF32 {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
         // the loop steps an LDS pointer only (the sorted index is derived
         // from it for the rare kept pair)
-        const Rec32* rp = l.r + (j0 - c0);
-        const Rec32* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
+        const float4* rp = l.a + (j0 - c0);
+        const float4* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
         for (; rp < re; ++rp) {
-            const float4 qa = rp->a;
-            const float4 qb = rp->b;
+            const float4 qa = rp[0];
+            const float4 qb = rp[W];
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
@@ -1166,8 +1166,8 @@ struct PolF32 {
     {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
         for (uint32_t j = j0; j < j1; ++j) {
-            const float4 qa = l.r[j - c0].a;
-            const float4 qb = l.r[j - c0].b;
+            const float4 qa = l.a[j - c0];
+            const float4 qb = l.b[j - c0];
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
