@@ -1060,7 +1060,8 @@ __global__ void k_screen_bounds(Plan p)
 // pair of kinds from a per-box table in LDS); otherwise the box's constant.
 template <bool K>
 struct PolF32 {
-    static constexpr int W = 160;         // staged records per chunk (5 KiB)
+    static constexpr int W = 128;         // staged records per chunk (4 KiB; measured
+                                          // against 96, 160, 192 and 256)
     static constexpr bool kScreen = true;
     static constexpr bool kKinds = K;
     static constexpr int kFlushBatch = 1;
