@@ -1064,8 +1064,8 @@ struct PolF32 {
                                           // against 96, 160, 192 and 256)
     static constexpr bool kScreen = true;
     static constexpr bool kKinds = K;
-    static constexpr int kFlushBatch = 1;
-    static constexpr bool kFlushSkipEmpty = false;
+    static constexpr int kFlushBatch = 2;
+    static constexpr bool kFlushSkipEmpty = true;
     static constexpr int kWaves = 6;
     // A staged candidate is two 16-byte halves in two arrays: a = x, y, z
     // relative to the group centre and vx; b = vy, vz, its kind (particle
@@ -1121,15 +1121,19 @@ struct PolF32 {
         }
     }
     // FP32 copy of a candidate: image-shifted position relative to X0 and
-    // velocity, each rounded once
+    // velocity, each rounded once.  Rows without an image (almost all) skip
+    // the shift (the row's shift is the same for the whole wave).
     __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev& B, const Group& g,
                                  int wx, int wy, int wz)
     {
         const P64 q = p.B[j];
-        const double sx = wx ? (double)wx * B.L[0] : 0.0, sy = wy ? (double)wy * B.L[1] : 0.0,
-                     sz = wz ? (double)wz * B.L[2] : 0.0;
-        l.a[t] = make_float4((float)((q.x + sx) - g.X0[0]), (float)((q.y + sy) - g.X0[1]),
-                             (float)((q.z + sz) - g.X0[2]), (float)q.vx);
+        double x = q.x, y = q.y, z = q.z;
+        if (wx | wy | wz) {
+            x = x + (wx ? (double)wx * B.L[0] : 0.0);
+            y = y + (wy ? (double)wy * B.L[1] : 0.0);
+            z = z + (wz ? (double)wz * B.L[2] : 0.0);
+        }
+        l.a[t] = make_float4((float)(x - g.X0[0]), (float)(y - g.X0[1]), (float)(z - g.X0[2]), (float)q.vx);
         l.b[t] = make_float4((float)q.vy, (float)q.vz, __uint_as_float(K ? (uint32_t)p.spB[j] : 0u),
                              __uint_as_float(j));
     }
