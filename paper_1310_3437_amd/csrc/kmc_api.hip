@@ -250,6 +250,7 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
     d.D2 = b.D2;
     d.dt = b.dt;
     d.dt_cap = b.dt;
+    for (int k = 0; k < 3; ++k) d.h[k] = d.L[k] / (double)b.ncell[k];
     d.dx = d.L[0] / (double)b.ncell[0];
     for (int k = 1; k < 3; ++k) {
         const double e = d.L[k] / (double)b.ncell[k];

@@ -1039,7 +1039,7 @@ __global__ void k_screen_bounds(Plan p)
     const double cells[3] = {66.0, 3.0, 3.0};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const double h = B.L[k] / (double)B.nc[k];
+        const double h = B.h[k];
         P[k] = 0.5 * cells[k] * h * (1.0 + 1e-9) + 1e-12 * (fabs(B.lo[k]) + fabs(B.hi[k]) + 2.0 * B.L[k]);
     }
     const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * 0x1.0p-24);
@@ -1080,6 +1080,7 @@ struct PolF32 {
     struct Own {
         float x, y, z, vx, vy, vz;   // position relative to the current group's centre
         uint32_t row;                // K: kMaxKinds * own kind
+        double X, Y, Z;              // own FP64 position (kept: reloading it per group costs more)
     };
     using Group = ScreenGroup;
     __device__ static P64 self64(const Plan& p, uint32_t i, const Own&) { return p.B[i]; }
@@ -1089,6 +1090,7 @@ struct PolF32 {
         o.vx = (float)m.vx; o.vy = (float)m.vy; o.vz = (float)m.vz;
         o.row = K ? (uint32_t)p.spB[i] * (uint32_t)kMaxKinds : 0u;
         x = m.x; y = m.y; z = m.z;
+        o.X = m.x; o.Y = m.y; o.Z = m.z;
     }
     // per-group LDS tables, written before the group's first staging barrier
     __device__ static void group_lds(Lds& l, const Plan& p, uint32_t gb, int lane)
@@ -1104,7 +1106,7 @@ struct PolF32 {
         const int clo[3] = {cxf - 1, gcy - 1, gcz - 1}, chi[3] = {cxl + 1, gcy + 1, gcz + 1};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const double h = B.L[k] / (double)B.nc[k];
+            const double h = B.h[k];
             g.X0[k] = B.lo[k] + 0.5 * (double)(clo[k] + chi[k] + 1) * h;
         }
         g.t = p.box_sb[gb];
@@ -1114,10 +1116,9 @@ struct PolF32 {
     {
         group_ctx(p, B, g, cxf, cxl, gcy, gcz, gb);
         if (in) {
-            const P64 m = p.B[i];
-            o.x = (float)(m.x - g.X0[0]);
-            o.y = (float)(m.y - g.X0[1]);
-            o.z = (float)(m.z - g.X0[2]);
+            o.x = (float)(o.X - g.X0[0]);
+            o.y = (float)(o.Y - g.X0[1]);
+            o.z = (float)(o.Z - g.X0[2]);
         }
     }
     // FP32 copy of a candidate: image-shifted position relative to X0 and

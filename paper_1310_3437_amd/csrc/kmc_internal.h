@@ -47,6 +47,7 @@ struct alignas(16) BoxDev {
     // (the adaptive rule's upper bound), dx the smallest cell edge
     // (hi_k - lo_k) / nc_k, time the simulated time since initialisation
     double dx, dt_cap, time;
+    double h[3];         // cell edges (hi_k - lo_k) / nc_k
 };
 
 // Flag on a particle id (ids stay below 2^31): the particle was absorbed by
