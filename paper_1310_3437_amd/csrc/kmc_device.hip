@@ -681,7 +681,8 @@ __device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64&
 
 // Candidate lists: per particle a count and up to kSlots entries (sorted
 // index of the other particle and the pair's FP64 key c2/g2, which is the
-// same from both sides); entry k of particle i lives at [k * N + i].
+// same from both sides, or +inf for a pair the FP32 screen kept and the exact
+// test rejected); entry k of particle i lives at [k * N + i].
 __device__ __forceinline__ void post_candidate(const Plan& p, uint32_t i, uint32_t j, double key)
 {
     const uint32_t k = atomicAdd(&p.sl_cnt[i], 1u);
@@ -757,6 +758,13 @@ struct Found {
         uint32_t j[kReg];
 #pragma unroll
         for (int k = 0; k < kReg; ++k) j[k] = k < n ? sj[64 * k] : 0u;
+        // list slots of the kept pairs claimed first: the atomics are in
+        // flight while the records load and the pairs are decided (a pair the
+        // FP64 test then rejects leaves an entry with key +inf, which never
+        // wins in the finish)
+        uint32_t slot[kReg];
+#pragma unroll
+        for (int k = 0; k < kReg; ++k) slot[k] = k < n ? atomicAdd(&p.sl_cnt[j[k]], 1u) : (uint32_t)kSlots;
         double key[kReg];
         bool acc[kReg];
 #pragma unroll
@@ -795,14 +803,11 @@ struct Found {
                 best = (int32_t)j[k];
             }
         }
-        uint32_t slot[kReg];
-#pragma unroll
-        for (int k = 0; k < kReg; ++k) slot[k] = acc[k] ? atomicAdd(&p.sl_cnt[j[k]], 1u) : (uint32_t)kSlots;
 #pragma unroll
         for (int k = 0; k < kReg; ++k) {
             if (slot[k] < (uint32_t)kSlots) {
                 SlotEntry e;
-                e.key = key[k];
+                e.key = acc[k] ? key[k] : __builtin_inf();
                 e.j = i;
                 e.pad_ = 0u;
                 p.sl[(size_t)slot[k] * p.N + j[k]] = e;
@@ -1467,8 +1472,9 @@ __global__ __launch_bounds__(256) void k_finish(Plan p)
             const SlotEntry e = p.sl[(size_t)k * p.N + i];
             const uint32_t j = e.j;
             const double key = e.key;
-            if (best < 0 || key < best_key ||
-                (key == best_key && p.idB[j] < p.idB[best])) {
+            // best_key is +inf while there is no best, so an entry with key
+            // +inf (a kept pair that the exact test rejected) never wins
+            if (key < best_key || (key == best_key && best >= 0 && p.idB[j] < p.idB[best])) {
                 best_key = key;
                 best = (int32_t)j;
             }
