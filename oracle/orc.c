@@ -91,10 +91,10 @@ static int64_t linear_cell(const orc_box* b, const int32_t c[3])
  *   b = r.g, g2 = |g|^2, c = r x g, c2 = |c|^2, each with the fixed fma order
  *   below (the only fused operations of the definition).
  * Closest approach of the straight relative path r + g t is at
- * t* = -b/g2 with squared distance d_min^2 = c2/g2.  The criteria
- * "reach the closest approach within the next step" (0 <= t* <= dt) and
- * "within the effective radii" (d_min^2 < D2 = sigma/pi) are evaluated
- * multiplied through by g2 > 0:  b <= 0, -b <= dt*g2, c2 < D2*g2.
+ * t* = -b/g2 with squared distance d_min^2 = c2/g2.  The criteria that the
+ * closest approach falls within the next step (0 <= t* <= dt) and inside the
+ * effective radii (d_min^2 < D2 = sigma/pi) are evaluated multiplied through
+ * by g2 > 0:  b <= 0, -b <= dt*g2, c2 < D2*g2.
  * The ordering key of an acceptable candidate is d_min^2 = c2/g2. */
 static void pair_q(const orc_box* b, const double pi[6], const double pj[6], const int32_t wrap[3], double D2,
                    orc_pair_q* q)
