@@ -232,20 +232,12 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
         d.nc[k] = b.ncell[k];
         d.periodic[k] = b.bc[k] == KMC_BC_PERIODIC ? 1 : 0;
         d.absorb[k] = b.bc[k] == KMC_BC_ABSORB ? 1 : 0;
-        d.ctr32[k] = (float)(0.5 * (b.lo[k] + b.hi[k]));
-        d.L32[k] = (float)d.L[k];
     }
-    // Screen input bounds.  Positions lie in [lo, hi]; the FP32 copy holds
-    // fl32(x - ctr) with |x - ctr| <= P.  For a neighbour pair |r_k| <= 2 h_k
-    // (plus rounding of the cell index); r_hat = fl(fl(xj_hat - xi_hat) + s_hat)
-    // errs by at most u (2 P + 2 |r| + 2 L) (periodic) or u (2 P + 2 |r|).
-    const double u = 0x1.0p-24;
+    // Bound on |r_k| for a neighbour pair (the FP32 screen's error bounds
+    // scale with it): two cell edges, plus rounding of the cell index.
     for (int k = 0; k < 3; ++k) {
         const double h = d.L[k] / (double)b.ncell[k];
         d.rmax[k] = 2.0 * h * (1.0 + 1e-9);
-        const double P = std::max(std::fabs(b.lo[k] - (double)d.ctr32[k]), std::fabs(b.hi[k] - (double)d.ctr32[k])) * (1.0 + 1e-9);
-        const double per = d.periodic[k] ? 2.0 * d.L[k] : 0.0;
-        d.er[k] = (float)(u * (2.0 * P + 2.0 * d.rmax[k] + per) * (1.0 + 1e-5));
     }
     d.D2 = b.D2;
     d.dt = b.dt;

@@ -449,9 +449,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
 }
 
 // --------------------------------------------------------------------------
-// a3: cell-sorted copy of the state as 48-byte records; for the FP32 screen
-// also an FP32 copy (positions relative to the box centre, velocities) and
-// the per-box bound on |v_k| that the screen's error bounds need.
+// a3: cell-sorted copy of the state as 48-byte records (ids and kinds beside
+// them); for the FP32 screen also the per-block bound on |fl32(v_k)| from
+// which the screen's error bounds per box are made.
 // --------------------------------------------------------------------------
 
 template <bool F32>
@@ -743,10 +743,11 @@ struct Found {
     }
     // Decide the kept pairs exactly in FP64 (the FP32 screen keeps pairs it
     // could not reject), write i's best among them (its forward best) and
-    // post each acceptable pair to the other particle's list.  The image
-    // shift is the one the search used (that of the two cells).  All lanes
-    // take the same branch-free path: loads first, then the arithmetic,
-    // then the posts.  Returns the number of pairs examined (statistics).
+    // post each kept pair to the other particle's list (key +inf when the
+    // exact test rejects it).  The image shift is the one the search used
+    // (that of the two cells).  All lanes take the same path: list slots
+    // claimed, records loaded, the arithmetic, then the list entries
+    // written.  Returns the number of pairs examined (statistics).
     // BATCH records are loaded at a time; SKIP: no loads for empty slots
     // (otherwise branch-free, loading the own record for them) -- measured
     // per precision

@@ -37,11 +37,7 @@ struct alignas(16) BoxDev {
     uint32_t poff;       // first global particle index of the box
     uint32_t n;          // particles in the box
     // FP32 screen constants
-    float ctr32[3];      // origin of the FP32 position copy (box centre)
-    float L32[3];        // periodic shift lengths, rounded to FP32
     float D2_32, dt_32;  // thresholds rounded to FP32
-    float er[3];         // bound on |r_hat_k - r_k| for any neighbour pair
-    float pad_;
     double rmax[3];      // bound on |r_k| for any neighbour pair (2 h_k)
     // time step: dt above is this step's; dt_cap is the box's configured step
     // (the adaptive rule's upper bound), dx the smallest cell edge
