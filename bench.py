@@ -100,6 +100,9 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests, search_mode=0):
         search_kernel_ms=search_kernel_ms,
         rechecks_per_step=(s1["rechecks"] - s0["rechecks"]) / steps,
         fallbacks=s1["fallbacks"] - s0["fallbacks"],
+        # pairs recorded per particle-step: FP64 the acceptable pairs, the
+        # FP32 screen the pairs it could not reject (decided again in FP64)
+        candidates_per_particle_step=(s1["candidates"] - s0["candidates"]) / (steps * w.n),
         history=[(int(a), int(b)) for a, b in zip(hn, hd)],
         pair_tests=pair_tests,
     )
