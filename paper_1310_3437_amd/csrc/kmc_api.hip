@@ -395,17 +395,30 @@ int kmc_step(kmc_ctx* c, uint32_t nsteps, void* stream)
             if (e == hipSuccess && le != hipSuccess) e = le;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) return KMC_EDEVICE;
+        if (e != hipSuccess) {
+            // drop a partial capture so the next call captures afresh
+            if (c->graph) (void)hipGraphDestroy(c->graph);
+            c->graph = nullptr;
+            c->exec = nullptr;
+            return KMC_EDEVICE;
+        }
     }
     for (uint32_t k = 0; k < nsteps; ++k) {
         hipError_t e;
         if (graph) {
             e = hipGraphLaunch(c->exec, s);
         } else if (c->cfg.profile) {
-            std::vector<hipEvent_t> set(KMC_PHASE_COUNT + 2);
-            for (auto& ev : set) {
+            std::vector<hipEvent_t> set;
+            set.reserve(KMC_PHASE_COUNT + 2);
+            while (set.size() < (size_t)KMC_PHASE_COUNT + 2) {
+                hipEvent_t ev = nullptr;
                 if (!c->ev_free.empty()) { ev = c->ev_free.back(); c->ev_free.pop_back(); }
-                else if (hipEventCreate(&ev) != hipSuccess) return KMC_EDEVICE;
+                else if (hipEventCreate(&ev) != hipSuccess) {
+                    // keep the events taken so far for later calls
+                    c->ev_free.insert(c->ev_free.end(), set.begin(), set.end());
+                    return KMC_EDEVICE;
+                }
+                set.push_back(ev);
             }
             e = launch_step(c->plan, s, set.data());
             c->ev_pending.push_back(std::move(set));
@@ -514,8 +527,8 @@ int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
         uint64_t tot = 0;
         for (int l = 0; l < kHistLanes; ++l) tot += acc[l];
         out->candidates = tot;
-    out->absorbed = ctl.absorbed_total;
     }
+    out->absorbed = ctl.absorbed_total;
     for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
     out->search_kernel_ms = c->search_kernel_ms;
     out->timed_steps = c->timed_steps;
