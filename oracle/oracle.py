@@ -181,11 +181,12 @@ def find_partners(box, state, ids=None, nthreads=0, brute=False, kinds=None):
     return out, tests
 
 
-def count_accepted(box, state, ids=None, nthreads=0):
+def count_accepted(box, state, ids=None, nthreads=0, kinds=None):
+    """Acceptable ordered pairs (and pair tests) of the cell-list search."""
     s = _soa(state)
     n = s.shape[1]
     ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
-    ob = make_box(box)
+    ob = make_box(box, kinds=kinds)
     ob.n = n
     acc = C.c_uint64(0)
     tests = C.c_uint64(0)

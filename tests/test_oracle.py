@@ -828,6 +828,54 @@ def test_mixture_cell_list_equals_bruteforce():
     assert np.array_equal(p, pb) and (p >= 0).sum() > 300
 
 
+def test_mixture_collision_rate_matches_kinetic_theory():
+    """Two kinds at one temperature (velocity components N(0, 1/m_s)): for
+    each pair of kinds (s, t) the expected number of unordered pairs with t*
+    in [0, dt] and d_min < rho_s + rho_t is n_st pi (rho_s + rho_t)^2 <g_st> dt
+    (unit volume), with n_st the number of such pairs and
+    <g_st> = sqrt(8/pi) sqrt(1/m_s + 1/m_t).  A wrong pair diameter or a
+    mixed-up kind fails the class it belongs to."""
+    N, N0 = 100_000, 60_000
+    a = 0.5 * N ** (-1.0 / 3.0)
+    radius, mass = (0.5 * a, 1.0 * a), (1.0, 4.0)
+    d = [[radius[s] + radius[t] for t in range(2)] for s in range(2)]
+    dmax = d[1][1]
+    nc = int(math.floor(1.0 / (1.1 * dmax)))
+    gm = [[math.sqrt(8.0 / math.pi) * math.sqrt(1.0 / mass[s] + 1.0 / mass[t]) for t in range(2)]
+          for s in range(2)]
+    npairs = {(0, 0): N0 * (N0 - 1) / 2, (0, 1): N0 * (N - N0), (1, 1): (N - N0) * (N - N0 - 1) / 2}
+    rate = {k: v * math.pi * d[k[0]][k[1]] ** 2 * gm[k[0]][k[1]] for k, v in npairs.items()}
+    dt = 500.0 / sum(rate.values())          # about 0.01 candidate pairs per particle
+    species = np.zeros(N, np.uint8)
+    species[N0:] = 1
+    seeds = 80
+    got = {k: 0 for k in rate}
+    for sd in range(seeds):
+        rng = np.random.default_rng(30_000 + sd)
+        s = np.empty((6, N))
+        s[0:3] = rng.random((3, N))
+        s[3:6] = rng.standard_normal((3, N)) / np.sqrt(np.asarray(mass)[species])
+        box = I.Box(n=N, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(nc,) * 3,
+                    periodic=(True,) * 3, D2=dmax * dmax, dt=dt)
+        acc, _ = O.count_accepted(box, s, kinds=(species, radius, mass))
+        only0 = s[:, :N0].copy()
+        only1 = s[:, N0:].copy()
+        b0 = I.Box(n=N0, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(nc,) * 3, periodic=(True,) * 3,
+                   D2=dmax * dmax, dt=dt)
+        b1 = I.Box(n=N - N0, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(nc,) * 3, periodic=(True,) * 3,
+                   D2=dmax * dmax, dt=dt)
+        a00, _ = O.count_accepted(b0, only0, kinds=(np.zeros(N0, np.uint8), radius, mass))
+        a11, _ = O.count_accepted(b1, only1, kinds=(np.ones(N - N0, np.uint8), radius, mass))
+        assert acc % 2 == 0 and a00 % 2 == 0 and a11 % 2 == 0
+        got[(0, 0)] += a00 // 2
+        got[(1, 1)] += a11 // 2
+        got[(0, 1)] += (acc - a00 - a11) // 2
+    for k, r in rate.items():
+        expect = r * dt * seeds
+        # about 8000 to 22000 pairs per class: 4% is over 3.5 standard deviations
+        assert abs(got[k] / expect - 1.0) < 0.04, (k, got[k], expect)
+
+
 def test_kinds_are_validated():
     s = _approach(0.02)
     for kinds in [(np.array([0, 2], np.uint8), (0.01, 0.03), (1.0, 1.0)),     # kind beyond the table
