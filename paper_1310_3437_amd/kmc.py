@@ -123,6 +123,10 @@ def load(path=LIB_PATH):
     if not os.path.exists(path):
         raise KmcError(f"{path} is missing: build it with __graft_entry__.build() "
                        "(there is no CPU fallback)")
+    # torch first: it ships its own HIP runtime, which the library then binds
+    # to (same soname).  Loaded the other way round the process would hold two
+    # runtimes, and torch's device pointers would be invalid in the library's.
+    import torch  # noqa: F401
     L = C.CDLL(path)
     vp, sz = C.c_void_p, C.c_size_t
     bp, cp = C.POINTER(KmcBox), C.POINTER(KmcConfig)

@@ -29,6 +29,21 @@ def test_library_exports_every_declared_function():
     assert L.kmc_abi_version() == 3
 
 
+def test_one_hip_runtime_whatever_the_import_order():
+    """kmc.load() before torch: the process must still hold one HIP runtime
+    (torch ships its own copy; two would make torch's device pointers
+    invalid in the library)."""
+    import subprocess
+    import sys
+    code = ("from paper_1310_3437_amd import kmc; kmc.load(); import torch; "
+            "maps = open('/proc/self/maps').read().split(chr(10)); "
+            "print(sorted({l.split()[-1] for l in maps if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    libs = eval(out.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1, libs
+
+
 def test_struct_sizes_match_header():
     # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes and the
     # species pointer; kmc_species: two u32, 2 x 8 doubles, a pointer
