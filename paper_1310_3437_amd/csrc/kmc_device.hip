@@ -58,7 +58,8 @@ __device__ __forceinline__ PairQ pair_q(double rx, double ry, double rz,
 
 // Partner criteria multiplied through by g2 > 0: closest approach within
 // [0, dt] (b <= 0, -b <= dt g2) and inside the interaction diameter
-// (c2 < D2 g2, i.e. d_min^2 < sigma/pi).
+// (c2 < D2 g2, i.e. d_min^2 < D2: sigma/pi for one kind of particle, the
+// squared sum of the two radii for particles of several kinds).
 __device__ __forceinline__ bool accept(const PairQ& q, double D2, double dt)
 {
     return (q.g2 > 0.0) & (q.b <= 0.0) & (-q.b <= dt * q.g2) & (q.c2 < D2 * q.g2);
@@ -389,7 +390,8 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_reduce(Plan p)
 }
 
 // One block of 1024 threads scans the block sums in place.  It also starts
-// the step's device-side bookkeeping (recheck list, work queue).
+// the step's device-side bookkeeping (recheck list, overflow pair list and
+// the FP32 screen's per-box velocity bounds).
 __global__ __launch_bounds__(1024) void k_scan_partials(Plan p)
 {
     __shared__ uint32_t lds[1024 / 64 + 1];
@@ -600,10 +602,12 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
 // (r, g and r x g change sign, b, g2, c2 do not), so every unordered pair is
 // tested once, from the particle whose cell comes first in a half
 // neighbourhood: its own row from the particle onwards through cell cx+1,
-// the row y+1 (cells cx-1..cx+1) and the three rows z+1 (y-1..y+1).  A pair
-// that passes is recorded in the candidate lists of both particles; a
-// per-particle finish pass then takes the exact FP64 (key, id) minimum, or,
-// for the FP32 screen, classifies the recorded candidates.
+// the row y+1 (cells cx-1..cx+1) and the three rows z+1 (y-1..y+1).  A lane
+// keeps the pairs that pass; at the end of the wave it decides them exactly
+// in FP64, writes the best of them (its forward best) and posts each
+// acceptable pair, with its key, to the other particle's candidate list.  A
+// per-particle finish pass then takes the (key, id) minimum of the forward
+// best and the list.
 //
 // One wave (= one block of 64 threads) takes 64 consecutive cell-sorted
 // particles, one per lane.  Lanes whose particles share a cell row form a
@@ -613,14 +617,16 @@ __global__ __launch_bounds__(256) void k_vmax_reduce(Plan p)
 // sub-range of the window from LDS.
 // --------------------------------------------------------------------------
 
-// Squared interaction diameter of the pair of sorted particles (i, j): the
-// box's D2 for one kind of particle, else (radius_s + radius_t)^2 of their
-// kinds (row = kMaxKinds * kind of i).
+// Row of sorted particle i's kind in the kind-pair tables (kMaxKinds * its
+// kind; 0 for one kind of particle).
 __device__ __forceinline__ uint32_t kind_row(const Plan& p, uint32_t i)
 {
     return p.nspecies ? (uint32_t)p.spB[i] * (uint32_t)kMaxKinds : 0u;
 }
 
+// Squared interaction diameter of the pair of sorted particles (i, j): the
+// box's D2 for one kind of particle, else (radius_s + radius_t)^2 of their
+// kinds.
 __device__ __forceinline__ double pair_D2(const Plan& p, const BoxDev& B, uint32_t row_i, uint32_t j)
 {
     return p.nspecies ? p.sp_D2[row_i + p.spB[j]] : B.D2;
@@ -709,12 +715,12 @@ __device__ __forceinline__ bool exact_key(const Plan& p, const BoxDev& B, uint32
     return true;
 }
 
-// Pairs a lane found, kept in registers until the end of the wave's search
-// (a global atomic or a division inside the search loop would stall the
-// whole wave); a lane that finds more appends the excess to the step's
-// overflow pair list (one counter, handled by k_distribute_overflow), or
-// raises the overflow flag when that list is full (whole-step FP64
-// fallback).
+// Pairs a lane found, kept until the end of the wave's search (the sorted
+// indices in LDS, the image shifts in a register: a global atomic or a
+// division inside the search loop would stall the whole wave); a lane that
+// finds more than kReg appends the excess to the step's overflow pair list
+// (one counter, handled by k_distribute_overflow), or raises the overflow
+// flag when that list is full (whole-step FP64 fallback).
 constexpr int kReg = 4;
 
 __device__ __forceinline__ uint32_t wcode(int wx, int wy, int wz)
@@ -924,6 +930,14 @@ struct PolF64 {
 // screen tests the Lagrange form d_min^2 g2 = |r|^2 g2 - b^2 (cheaper than the
 // cross product) and drops a pair only when the FP64 definition is certain to
 // reject it; every pair it keeps is decided exactly in FP64 afterwards.
+//
+// A screened group spans at most kScreenGroupCells cells along x (the search
+// closes a group there and starts the next one with the row's remaining
+// lanes), so its neighbourhood spans at most kScreenGroupCells + 2 cells; the
+// error bounds rest on this.  Without the limit a sparse row (under one
+// particle per cell) could put a wave's lanes hundreds of cells apart.
+constexpr int kScreenGroupCells = 64;
+
 struct ScreenGroup {
     double X0[3];
     ScreenBounds t;
@@ -933,9 +947,9 @@ struct ScreenGroup {
 // of any search group of the box (forward error analysis, Higham 2002,
 // ch. 3).  Inputs: |r_k| <= R_k = 2 h_k; FP32 position errors
 // e_r,k = u (2 P_k + 2 R_k) with positions relative to the group centre X0
-// (a group spans at most 64 cells along x, so |x - X0| <= P_x = 33 h_x,
-// P_y = 1.5 h_y, P_z = 1.5 h_z) plus the FP64 definition's own input
-// rounding; velocity-difference error e_g = 4 u V.
+// (a group spans at most kScreenGroupCells = 64 cells along x, so
+// |x - X0| <= P_x = 33 h_x, P_y = 1.5 h_y, P_z = 1.5 h_z) plus the FP64
+// definition's own input rounding; velocity-difference error e_g = 4 u V.
 // With q = sqrt(g2_hat) (kappa q bounds every |g_hat_k|):
 //   |db|   <= b0 + b1 q
 //   |dg2|  <= g0 + g1 q + g2c q^2
@@ -1042,7 +1056,8 @@ __global__ void k_screen_bounds(Plan p)
     if (b >= p.nboxes) return;
     const BoxDev& B = p.boxes[b];
     double P[3];
-    const double cells[3] = {66.0, 3.0, 3.0};
+    // neighbourhood of a group in cells (its own cells and one on each side)
+    const double cells[3] = {(double)(kScreenGroupCells + 2), 3.0, 3.0};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double h = B.h[k];
@@ -1150,8 +1165,8 @@ struct PolF32 {
                                 Found& f)
     {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
-        // the loop steps an LDS pointer only (the sorted index is derived
-        // from it for the rare kept pair)
+        // the loop steps an LDS pointer only; the sorted index is read from
+        // the staged record for a kept pair alone
         const float4* rp = l.a + (j0 - c0);
         const float4* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
         for (; rp < re; ++rp) {
@@ -1242,14 +1257,18 @@ void k_search_half(Plan p)
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
-        const uint64_t grp = __ballot(alive && rowkey == key) & remaining;
+        const int cxf = __builtin_amdgcn_readlane(cx, lead);
+        // the row's lanes in ascending cells; a screened group ends after
+        // kScreenGroupCells cells and the rest of the row forms the next one
+        const uint64_t grp =
+            __ballot(alive && rowkey == key && (!Pol::kScreen || cx - cxf < kScreenGroupCells)) & remaining;
         remaining &= ~grp;
         const bool in = (grp >> lane) & 1ull;
         const int last = 63 - __clzll((long long)grp);
         const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
         const BoxDev& B = p.boxes[gb];
         const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
-        const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
+        const int cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
         Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
@@ -1355,14 +1374,18 @@ void k_search_full(Plan p)
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
-        const uint64_t grp = __ballot(alive && rowkey == key) & remaining;
+        const int cxf = __builtin_amdgcn_readlane(cx, lead);
+        // the row's lanes in ascending cells; a screened group ends after
+        // kScreenGroupCells cells and the rest of the row forms the next one
+        const uint64_t grp =
+            __ballot(alive && rowkey == key && (!Pol::kScreen || cx - cxf < kScreenGroupCells)) & remaining;
         remaining &= ~grp;
         const bool in = (grp >> lane) & 1ull;
         const int last = 63 - __clzll((long long)grp);
         const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
         const BoxDev& B = p.boxes[gb];
         const int gcy = __builtin_amdgcn_readlane(cy, lead), gcz = __builtin_amdgcn_readlane(cz, lead);
-        const int cxf = __builtin_amdgcn_readlane(cx, lead), cxl = __builtin_amdgcn_readlane(cx, last);
+        const int cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
         Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);

@@ -102,6 +102,63 @@ def test_screen_exact_on_adversarial_pairs(kmc, variant, mode):
     assert stats["candidates"] >= s64["candidates"]
 
 
+def adversarial_sparse_row(seed=0, spacing=200, nx=30000, kinds=("radius", "tend", "tzero")):
+    """Near-boundary pairs along one sparse cell row: a pair every `spacing`
+    cells of an nx-cell periodic x axis (cell edge 1/30), so that the 64
+    consecutive particles of a wave lie thousands of cells apart.  The FP32
+    screen's error bounds hold for search groups of at most 64 cells along
+    x, which the search enforces by splitting such rows."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / 30.0
+    D = 0.9 * h
+    dt = 0.01
+    pts = []
+    for a in range(nx // spacing):
+        ctr = np.array([(spacing * a + 1.5) * h, 1.5 * h, 1.5 * h])
+        kind = kinds[rng.integers(len(kinds))]
+        gdir = rng.standard_normal(3)
+        gdir /= np.linalg.norm(gdir)
+        perp = np.cross(gdir, rng.standard_normal(3))
+        perp /= np.linalg.norm(perp)
+        gmag = rng.uniform(0.5, 2.0)
+        eps = 2.0 ** -rng.integers(18, 51) * (1 if rng.random() < 0.5 else -1)
+        if kind == "radius":
+            t0, d = rng.uniform(0.2, 0.8) * dt, D * (1 + eps)
+        elif kind == "tend":
+            t0, d = dt * (1 + eps), D * rng.uniform(0.1, 0.9)
+        else:
+            t0, d = eps * dt, D * rng.uniform(0.1, 0.9)
+        g = gdir * gmag
+        r = -g * t0 + perp * d
+        pts.append((ctr - r / 2, -g / 2))
+        pts.append((ctr + r / 2, g / 2))
+    n = len(pts)
+    s = np.empty((6, n))
+    for k, (x, v) in enumerate(pts):
+        s[0:3, k] = x
+        s[3:6, k] = v
+    L = (nx * h, 3 * h, 3 * h)
+    for k in range(3):
+        s[k] = np.mod(s[k], L[k])
+    box = I.Box(n=n, lo=(0.0, 0.0, 0.0), hi=L, ncell=(nx, 3, 3), periodic=(True,) * 3, D2=D * D, dt=dt)
+    perm = rng.permutation(n)
+    return I.Workload("adversarial_sparse_row", [box], s[:, perm].copy(), 1)
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+def test_screen_exact_on_a_sparse_row(kmc, mode):
+    w = adversarial_sparse_row(seed=13)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    print(f"\n[screen] sparse row N={w.n} search={mode}", flush=True)
+    mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2, search_mode=sm)
+    assert mism64 == 0 and st64
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
+    print(f"[screen] mismatches={mism} candidates fp32={stats['candidates']} fp64={s64['candidates']}",
+          flush=True)
+    assert mism == 0 and same
+    assert stats["candidates"] >= s64["candidates"]
+
+
 @pytest.mark.parametrize("mode", ["half", "full"])
 def test_negative_control_without_error_bounds(kmc, mode):
     """With the error bounds disabled the FP32 screen decides near-boundary
