@@ -463,6 +463,7 @@ __global__ void k_scatter(Plan p)
     const bool valid = i < p.N;
     const size_t N = p.N;
     float vm = 0.f;
+    bool outside = false;
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (valid) {
         const uint32_t d = p.start[p.cell[i]] + p.slot[i];
@@ -478,11 +479,24 @@ __global__ void k_scatter(Plan p)
         p.idB[d] = id;
         if (p.spA) p.spB[d] = p.spA[i];
         if (id & kGone) vx = vy = vz = 0.0;   // not in the gas: no part in the adaptive step
-        if (F32) vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
+        if (F32) {
+            vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
+            // The screen's error bounds take every particle to lie inside the
+            // cell it is binned in.  A particle outside its box's grid (placed
+            // there, or moved more than a box length in one step) is binned in
+            // an end cell; the step's partners then come from the whole-step
+            // FP64 search instead.
+            if (!(id & kGone)) {
+                const BoxDev& B = box_of(p, i);
+                outside = !(r.x >= B.lo[0] && r.x <= B.hi[0] && r.y >= B.lo[1] && r.y <= B.hi[1] &&
+                            r.z >= B.lo[2] && r.z <= B.hi[2]);
+            }
+        }
     }
     __shared__ float wmax[16];
     __shared__ unsigned long long wv2[16];
     if (F32) {
+        if (__ballot(outside) && (threadIdx.x & 63) == 0) atomicOr(&p.ctl->overflow, 1u);
         // per-block maximum of |fl32(v_k)|; k_vmax_reduce folds the blocks of each box
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off, 64));
@@ -1575,8 +1589,9 @@ __global__ void k_recheck64(Plan p)
     }
 }
 
-// Whole-step FP64 search when the recheck list overflowed (exits at once
-// otherwise).
+// Whole-step FP64 search when the recheck list or the overflow pair list
+// overflowed, or a particle lies outside its box's grid under the FP32
+// screen (exits at once otherwise).
 __global__ void k_fallback64(Plan p)
 {
     if (p.ctl->overflow == 0u) return;
@@ -1855,10 +1870,9 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         k_finish<<<blocks_for(p.N, 256), 256, 0, s>>>(p);
     }
     mark(KMC_PHASE_RECHECK);
-    if (p.N > 0 && !full) {
-        k_recheck64<<<128, 256, 0, s>>>(p);
-        k_fallback64<<<512, 256, 0, s>>>(p);
-    }
+    if (p.N > 0 && !full) k_recheck64<<<128, 256, 0, s>>>(p);
+    // (the full search raises no overflow; the FP32 sorted copy may)
+    if (p.N > 0 && (!full || p.precision == KMC_FP32_SCREEN)) k_fallback64<<<512, 256, 0, s>>>(p);
     mark(KMC_PHASE_RESOLVE);
     if (p.N > 0) {
         if (p.nspecies > 0) k_resolve<true><<<gN, b, 0, s>>>(p);

@@ -159,6 +159,35 @@ def test_screen_exact_on_a_sparse_row(kmc, mode):
     assert stats["candidates"] >= s64["candidates"]
 
 
+def adversarial_outside(seed=0, lengths=100):
+    """The adversarial pairs of the periodic 30^3 grid, with the pairs of the
+    last lattice column moved `lengths` box lengths beyond hi along x: they
+    are binned in the last cell (cells clamp), far from it.  A single wrap at
+    the end of a step does not bring them back, so they stay outside."""
+    w = adversarial(seed=seed, kinds=("radius", "tend", "tzero"))
+    s = w.state.copy()
+    b = w.boxes[0]
+    L = b.hi[0] - b.lo[0]
+    h = L / b.ncell[0]
+    far = s[0] >= b.lo[0] + 27 * h          # lattice column a = 9 (cells 27..29)
+    s[0, far] += lengths * L
+    return I.Workload("adversarial_outside", [b], s, 1), int(far.sum())
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+def test_screen_exact_with_particles_outside_the_grid(kmc, mode):
+    w, nfar = adversarial_outside(seed=16)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    print(f"\n[screen] {nfar} particles outside the grid, N={w.n} search={mode}", flush=True)
+    mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2, search_mode=sm)
+    assert mism64 == 0 and st64 and s64["fallbacks"] == 0
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
+    print(f"[screen] mismatches={mism} fallbacks={stats['fallbacks']}", flush=True)
+    assert mism == 0 and same
+    # both steps had particles outside: the FP32 path took the FP64 search
+    assert stats["fallbacks"] == 2
+
+
 @pytest.mark.parametrize("mode", ["half", "full"])
 def test_negative_control_without_error_bounds(kmc, mode):
     """With the error bounds disabled the FP32 screen decides near-boundary
