@@ -1079,14 +1079,38 @@ __global__ void k_screen_bounds(Plan p)
     }
     const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * 0x1.0p-24);
     double tc1, RRb;
-    screen_thresholds(B, P, V, p.guard, p.box_sb[b], tc1, RRb);
+    ScreenBounds g;
+    screen_thresholds(B, P, V, p.guard, g, tc1, RRb);
+    p.box_sb[b] = g;
+    // The bounds take FP32 arithmetic to neither overflow nor lose to
+    // underflow more than a small fraction of them: cell edges in
+    // [2^-40, 2^40], the largest speed 0 or in [2^-40, 2^40], the pair test's
+    // largest products (|r|^2 g2 <= 144 h^2 V^2 and the folded thresholds
+    // times g2 <= 12 V^2) below 2^120, every threshold finite.  Outside that
+    // range this step's partners come from the whole-step FP64 search.
+    const double lo_s = 0x1.0p-40, hi_s = 0x1.0p40, big = 0x1.0p120;
+    bool safe = V == 0.0 || (V >= lo_s && V <= hi_s);
+    double hmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        safe = safe && B.h[k] >= lo_s && B.h[k] <= hi_s;
+        hmax = fmax(hmax, B.h[k]);
+    }
+    const double g2max = 12.0 * V * V;
+    safe = safe && 256.0 * hmax * hmax * g2max < big;
+    const float th[8] = {g.tb0, g.tb1, g.tt0, g.tt1, g.tc0, g.tc1, g.kdt, g.kD2};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) safe = safe && isfinite(th[k]) && (double)fabsf(th[k]) * g2max < big;
     if (p.nspecies > 0) {
         // the folded constant of each pair of kinds, from the pair's own D2
         // rounded to FP32 (entries of absent kinds are never read)
         float* tab = p.box_kD2 + (size_t)b * (kMaxKinds * kMaxKinds);
-        for (int e = 0; e < kMaxKinds * kMaxKinds; ++e)
+        for (int e = 0; e < kMaxKinds * kMaxKinds; ++e) {
             tab[e] = fold_kD2((double)(float)p.sp_D2[e], tc1, RRb);
+            safe = safe && isfinite(tab[e]) && (double)tab[e] * g2max < big;
+        }
     }
+    if (!safe) atomicOr(&p.ctl->overflow, 1u);
 }
 
 
@@ -1590,8 +1614,9 @@ __global__ void k_recheck64(Plan p)
 }
 
 // Whole-step FP64 search when the recheck list or the overflow pair list
-// overflowed, or a particle lies outside its box's grid under the FP32
-// screen (exits at once otherwise).
+// overflowed, or, under the FP32 screen, a particle lies outside its box's
+// grid or a box's scales leave the screen's safe range (exits at once
+// otherwise).
 __global__ void k_fallback64(Plan p)
 {
     if (p.ctl->overflow == 0u) return;

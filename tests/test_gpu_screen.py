@@ -188,6 +188,39 @@ def test_screen_exact_with_particles_outside_the_grid(kmc, mode):
     assert stats["fallbacks"] == 2
 
 
+def scaled(w, pos=1.0, vel=1.0):
+    """The workload in other units: positions times `pos`, velocities times
+    `vel`, dt times pos / vel.  Powers of two scale the FP64 definition
+    exactly, so the partners are those of the unscaled workload."""
+    b = w.boxes[0]
+    s = w.state.copy()
+    s[0:3] *= pos
+    s[3:6] *= vel
+    box = I.Box(n=b.n, lo=tuple(pos * x for x in b.lo), hi=tuple(pos * x for x in b.hi), ncell=b.ncell,
+                periodic=b.periodic, D2=b.D2 * pos * pos, dt=b.dt * pos / vel)
+    return I.Workload(w.name + "_scaled", [box], s, w.seed)
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("units", [dict(pos=2.0 ** -50), dict(vel=2.0 ** 70)], ids=["tiny_lengths", "huge_speeds"])
+def test_screen_exact_outside_its_safe_range(kmc, units, mode):
+    """Cell edges below 2^-40 (FP32 thresholds would underflow) or speeds
+    above 2^40 (FP32 products would overflow): the FP32 path takes the FP64
+    search for every step and stays exact."""
+    base = adversarial(seed=19, kinds=("radius", "tend", "tzero"))
+    w = scaled(base, **units)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    print(f"\n[screen] units {units} N={w.n} search={mode}", flush=True)
+    mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
+    print(f"[screen] mismatches={mism} fallbacks={stats['fallbacks']}", flush=True)
+    assert mism == 0 and same and stats["fallbacks"] == 2
+    # the units do not change the oracle's partners
+    ra, rb = O.Run(base), O.Run(w)
+    ra.step()
+    rb.step()
+    assert np.array_equal(ra.partner_by_id, rb.partner_by_id)
+
+
 @pytest.mark.parametrize("mode", ["half", "full"])
 def test_negative_control_without_error_bounds(kmc, mode):
     """With the error bounds disabled the FP32 screen decides near-boundary
