@@ -57,6 +57,14 @@ typedef enum {
     KMC_ESTATE = -5      /* call not valid in the context's current state          */
 } kmc_status;
 
+/* KMC_FP64: the pair test in binary64.
+ * KMC_FP32_SCREEN: the search tests pairs in FP32 against rigorous bounds on
+ *   the rounding error and decides every pair it keeps in FP64, so the
+ *   partners are those of KMC_FP64 bit for bit.  A step that breaks an
+ *   assumption of the bounds takes the whole-step FP64 search instead
+ *   (counted in kmc_stats.fallbacks).  That happens when a particle lies
+ *   outside its box's grid, or when a box's cell edges or largest speed
+ *   fall outside [2^-40, 2^40] (a speed of 0 is fine). */
 typedef enum { KMC_FP64 = 0, KMC_FP32_SCREEN = 1 } kmc_precision;
 typedef enum { KMC_GEOM_BOX = 0, KMC_GEOM_SPHERE = 1 } kmc_geometry;
 typedef enum { KMC_BC_REFLECT = 0, KMC_BC_PERIODIC = 1, KMC_BC_ABSORB = 2 } kmc_bc;
@@ -219,7 +227,8 @@ typedef struct kmc_stats {
     uint64_t n_total;          /* particles over all boxes                              */
     uint64_t cells_total;      /* cells over all boxes                                  */
     uint64_t rechecks;         /* particles re-searched in full FP64 (sum over steps)   */
-    uint64_t fallbacks;        /* steps whose recheck list overflowed                   */
+    uint64_t fallbacks;        /* steps that took the whole-step FP64 search (a list
+                                  overflowed, or the FP32 screen's assumptions failed)  */
     double ms[8];              /* accumulated milliseconds per phase (profile mode)      */
     uint64_t timed_steps;      /* steps that contributed to ms                          */
     double search_kernel_ms;   /* accumulated milliseconds of the search kernel alone   */
