@@ -255,6 +255,29 @@ def test_cell_list_equals_bruteforce(periodic):
         assert np.array_equal(pc, pb), f"trial {trial}"
 
 
+@pytest.mark.parametrize("periodic", [True, False])
+def test_particles_outside_the_grid_bin_in_the_end_cells(periodic):
+    """A position outside [lo, hi] is binned in the end cell of that axis
+    (the cell index clamps), and the cell-list search still equals brute
+    force over the same cells."""
+    rng = np.random.default_rng(777 if periodic else 778)
+    for trial in range(40):
+        n = int(rng.integers(2, 400))
+        nc = int(rng.integers(3, 8))
+        h = 1.0 / nc
+        D = h * float(rng.uniform(0.3, 1.0))
+        dt = float(rng.uniform(0.01, 0.3)) * h
+        box, s = _rand_box(rng, n, periodic, nc, D, dt)
+        out = rng.random(n) < 0.2
+        ax = rng.integers(0, 3, n)
+        for i in np.nonzero(out)[0]:
+            s[ax[i], i] += (1.0 if rng.random() < 0.5 else -1.0) * float(rng.uniform(1.0, 3.0))
+        ids = rng.permutation(n).astype(np.uint32)
+        pc, _ = O.find_partners(box, s, ids, nthreads=4)
+        pb, _ = O.find_partners(box, s, ids, brute=True)
+        assert np.array_equal(pc, pb), f"trial {trial}"
+
+
 def test_search_independent_of_particle_order_and_threads():
     rng = np.random.default_rng(7)
     box, s = _rand_box(rng, 3000, True, 8, 0.11, 0.02)
