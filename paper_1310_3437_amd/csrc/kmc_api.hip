@@ -172,7 +172,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.box_vmax = (unsigned int*)take(sizeof(unsigned int) * nboxes);
     p.v2_part = (unsigned long long*)take(sizeof(unsigned long long) * (nblk_part ? nblk_part : 1));
     p.box_v2 = (unsigned long long*)take(sizeof(unsigned long long) * nboxes);
-    p.box_sb = (ScreenBounds*)take(sizeof(ScreenBounds) * nboxes);
+    p.box_sb = (ScreenBounds*)take(sizeof(ScreenBounds) * kSpanClasses * nboxes);
     p.idA = (uint32_t*)take(4 * N);
     p.idB = (uint32_t*)take(4 * N);
     p.cell = (uint32_t*)take(4 * N);
@@ -195,7 +195,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
         p.spB = (uint8_t*)take(N ? N : 1);
         p.sp_D2 = (const double*)take(sizeof(double) * kMaxKinds * kMaxKinds);
         p.sp_mass = (const double*)take(sizeof(double) * kMaxKinds);
-        p.box_kD2 = (float*)take(sizeof(float) * kMaxKinds * kMaxKinds * nboxes);
+        p.box_kD2 = (float*)take(sizeof(float) * kMaxKinds * kMaxKinds * kSpanClasses * nboxes);
     } else {
         p.spA = p.spB = nullptr;
         p.sp_D2 = p.sp_mass = nullptr;

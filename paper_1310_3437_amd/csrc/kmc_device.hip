@@ -945,12 +945,21 @@ struct PolF64 {
 // cross product) and drops a pair only when the FP64 definition is certain to
 // reject it; every pair it keeps is decided exactly in FP64 afterwards.
 //
-// A screened group spans at most kScreenGroupCells cells along x (the search
-// closes a group there and starts the next one with the row's remaining
-// lanes), so its neighbourhood spans at most kScreenGroupCells + 2 cells; the
-// error bounds rest on this.  Without the limit a sparse row (under one
-// particle per cell) could put a wave's lanes hundreds of cells apart.
-constexpr int kScreenGroupCells = 64;
+// The bounds depend on how far a group's neighbourhood reaches along x.  A
+// screened group of at most span_cells(c) cells uses the thresholds of class
+// c (k_screen_bounds computes each class per box), so dense rows keep tight
+// bounds while the lanes of a sparse row (under one particle per cell),
+// hundreds of cells apart, share looser ones; the search splits rows wider
+// than the last class.
+__host__ __device__ constexpr int span_cells(int c) { return 64 << (2 * c); }
+constexpr int kScreenGroupCells = span_cells(kSpanClasses - 1);
+
+__device__ __forceinline__ uint32_t span_class(int cells)
+{
+    uint32_t c = 0;
+    while (c + 1 < (uint32_t)kSpanClasses && cells > span_cells((int)c)) ++c;
+    return c;
+}
 
 struct ScreenGroup {
     double X0[3];
@@ -961,9 +970,10 @@ struct ScreenGroup {
 // of any search group of the box (forward error analysis, Higham 2002,
 // ch. 3).  Inputs: |r_k| <= R_k = 2 h_k; FP32 position errors
 // e_r,k = u (2 P_k + 2 R_k) with positions relative to the group centre X0
-// (a group spans at most kScreenGroupCells = 64 cells along x, so
-// |x - X0| <= P_x = 33 h_x, P_y = 1.5 h_y, P_z = 1.5 h_z) plus the FP64
-// definition's own input rounding; velocity-difference error e_g = 4 u V.
+// (a group of class c spans at most s = span_cells(c) cells along x, so
+// |x - X0| <= P_x = (s/2 + 1) h_x, P_y = 1.5 h_y, P_z = 1.5 h_z) plus the
+// FP64 definition's own input rounding; velocity-difference error
+// e_g = 4 u V.
 // With q = sqrt(g2_hat) (kappa q bounds every |g_hat_k|):
 //   |db|   <= b0 + b1 q
 //   |dg2|  <= g0 + g1 q + g2c q^2
@@ -1069,19 +1079,7 @@ __global__ void k_screen_bounds(Plan p)
     const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= p.nboxes) return;
     const BoxDev& B = p.boxes[b];
-    double P[3];
-    // neighbourhood of a group in cells (its own cells and one on each side)
-    const double cells[3] = {(double)(kScreenGroupCells + 2), 3.0, 3.0};
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double h = B.h[k];
-        P[k] = 0.5 * cells[k] * h * (1.0 + 1e-9) + 1e-12 * (fabs(B.lo[k]) + fabs(B.hi[k]) + 2.0 * B.L[k]);
-    }
     const double V = (double)__uint_as_float(p.box_vmax[b]) * (1.0 + 3.0 * 0x1.0p-24);
-    double tc1, RRb;
-    ScreenBounds g;
-    screen_thresholds(B, P, V, p.guard, g, tc1, RRb);
-    p.box_sb[b] = g;
     // The bounds take FP32 arithmetic to neither overflow nor lose to
     // underflow more than a small fraction of them: cell edges in
     // [2^-40, 2^40], the largest speed 0 or in [2^-40, 2^40], the pair test's
@@ -1098,16 +1096,29 @@ __global__ void k_screen_bounds(Plan p)
     }
     const double g2max = 12.0 * V * V;
     safe = safe && 256.0 * hmax * hmax * g2max < big;
-    const float th[8] = {g.tb0, g.tb1, g.tt0, g.tt1, g.tc0, g.tc1, g.kdt, g.kD2};
+    for (int c = 0; c < kSpanClasses; ++c) {
+        // neighbourhood of a group of this class in cells (its own cells and
+        // one on each side)
+        const double cells[3] = {(double)(span_cells(c) + 2), 3.0, 3.0};
+        double P[3];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) safe = safe && isfinite(th[k]) && (double)fabsf(th[k]) * g2max < big;
-    if (p.nspecies > 0) {
-        // the folded constant of each pair of kinds, from the pair's own D2
-        // rounded to FP32 (entries of absent kinds are never read)
-        float* tab = p.box_kD2 + (size_t)b * (kMaxKinds * kMaxKinds);
-        for (int e = 0; e < kMaxKinds * kMaxKinds; ++e) {
-            tab[e] = fold_kD2((double)(float)p.sp_D2[e], tc1, RRb);
-            safe = safe && isfinite(tab[e]) && (double)tab[e] * g2max < big;
+        for (int k = 0; k < 3; ++k)
+            P[k] = 0.5 * cells[k] * B.h[k] * (1.0 + 1e-9) + 1e-12 * (fabs(B.lo[k]) + fabs(B.hi[k]) + 2.0 * B.L[k]);
+        double tc1, RRb;
+        ScreenBounds g;
+        screen_thresholds(B, P, V, p.guard, g, tc1, RRb);
+        p.box_sb[(size_t)b * kSpanClasses + c] = g;
+        const float th[8] = {g.tb0, g.tb1, g.tt0, g.tt1, g.tc0, g.tc1, g.kdt, g.kD2};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) safe = safe && isfinite(th[k]) && (double)fabsf(th[k]) * g2max < big;
+        if (p.nspecies > 0) {
+            // the folded constant of each pair of kinds, from the pair's own D2
+            // rounded to FP32 (entries of absent kinds are never read)
+            float* tab = p.box_kD2 + ((size_t)b * kSpanClasses + c) * (kMaxKinds * kMaxKinds);
+            for (int e = 0; e < kMaxKinds * kMaxKinds; ++e) {
+                tab[e] = fold_kD2((double)(float)p.sp_D2[e], tc1, RRb);
+                safe = safe && isfinite(tab[e]) && (double)tab[e] * g2max < big;
+            }
         }
     }
     if (!safe) atomicOr(&p.ctl->overflow, 1u);
@@ -1152,15 +1163,16 @@ struct PolF32 {
         o.X = m.x; o.Y = m.y; o.Z = m.z;
     }
     // per-group LDS tables, written before the group's first staging barrier
-    __device__ static void group_lds(Lds& l, const Plan& p, uint32_t gb, int lane)
+    // (sbi: the group's threshold set, box * kSpanClasses + span class)
+    __device__ static void group_lds(Lds& l, const Plan& p, uint32_t sbi, int lane)
     {
-        if (K) l.kd2[lane] = p.box_kD2[(size_t)gb * (kMaxKinds * kMaxKinds) + (uint32_t)lane];
+        if (K) l.kd2[lane] = p.box_kD2[(size_t)sbi * (kMaxKinds * kMaxKinds) + (uint32_t)lane];
     }
-    // Centre and thresholds of the group whose cells are x in [cxf, cxl] of
-    // row (gcy, gcz); its neighbourhood spans cells cxf-1..cxl+1, gcy-1..gcy+1,
-    // gcz-1..gcz+1 (images included).
+    // Centre and thresholds (set sbi) of the group whose cells are x in
+    // [cxf, cxl] of row (gcy, gcz); its neighbourhood spans cells
+    // cxf-1..cxl+1, gcy-1..gcy+1, gcz-1..gcz+1 (images included).
     __device__ static void group_ctx(const Plan& p, const BoxDev& B, Group& g, int cxf, int cxl, int gcy, int gcz,
-                                     int gb)
+                                     int sbi)
     {
         const int clo[3] = {cxf - 1, gcy - 1, gcz - 1}, chi[3] = {cxl + 1, gcy + 1, gcz + 1};
 #pragma unroll
@@ -1168,12 +1180,12 @@ struct PolF32 {
             const double h = B.h[k];
             g.X0[k] = B.lo[k] + 0.5 * (double)(clo[k] + chi[k] + 1) * h;
         }
-        g.t = p.box_sb[gb];
+        g.t = p.box_sb[sbi];
     }
     __device__ static void begin_group(const Plan& p, const BoxDev& B, Own& o, Group& g, int cxf, int cxl,
-                                       int gcy, int gcz, int gb, uint32_t i, bool in)
+                                       int gcy, int gcz, int sbi, uint32_t i, bool in)
     {
-        group_ctx(p, B, g, cxf, cxl, gcy, gcz, gb);
+        group_ctx(p, B, g, cxf, cxl, gcy, gcz, sbi);
         if (in) {
             o.x = (float)(o.X - g.X0[0]);
             o.y = (float)(o.Y - g.X0[1]);
@@ -1297,7 +1309,8 @@ void k_search_half(Plan p)
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
         const int cxf = __builtin_amdgcn_readlane(cx, lead);
         // the row's lanes in ascending cells; a screened group ends after
-        // kScreenGroupCells cells and the rest of the row forms the next one
+        // kScreenGroupCells cells (the rest of the row forms the next one),
+        // and its span picks its class of screen thresholds
         const uint64_t grp =
             __ballot(alive && rowkey == key && (!Pol::kScreen || cx - cxf < kScreenGroupCells)) & remaining;
         remaining &= ~grp;
@@ -1309,8 +1322,9 @@ void k_search_half(Plan p)
         const int cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
-        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
-        Pol::group_lds(lds, p, gb, lane);
+        const uint32_t sbi = gb * (uint32_t)kSpanClasses + span_class(cxl - cxf + 1);
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)sbi, i, in);
+        Pol::group_lds(lds, p, sbi, lane);
         // Cells [ca, cb] of a row seen with image shift (wx, wy, wz); each lane
         // tests the sub-range [ls, le) of it (empty when ls >= le).
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz, int dy,
@@ -1414,7 +1428,8 @@ void k_search_full(Plan p)
         const uint32_t key = (uint32_t)__builtin_amdgcn_readlane((int)rowkey, lead);
         const int cxf = __builtin_amdgcn_readlane(cx, lead);
         // the row's lanes in ascending cells; a screened group ends after
-        // kScreenGroupCells cells and the rest of the row forms the next one
+        // kScreenGroupCells cells (the rest of the row forms the next one),
+        // and its span picks its class of screen thresholds
         const uint64_t grp =
             __ballot(alive && rowkey == key && (!Pol::kScreen || cx - cxf < kScreenGroupCells)) & remaining;
         remaining &= ~grp;
@@ -1426,8 +1441,9 @@ void k_search_full(Plan p)
         const int cxl = __builtin_amdgcn_readlane(cx, last);
         const int NX = B.nc[0], NY = B.nc[1], NZ = B.nc[2];
         typename Pol::Group gctx;
-        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)gb, i, in);
-        Pol::group_lds(lds, p, gb, lane);
+        const uint32_t sbi = gb * (uint32_t)kSpanClasses + span_class(cxl - cxf + 1);
+        Pol::begin_group(p, B, own, gctx, cxf, cxl, gcy, gcz, (int)sbi, i, in);
+        Pol::group_lds(lds, p, sbi, lane);
         auto part = [&](uint32_t row, int ca, int cb, uint32_t ls, uint32_t le, int wx, int wy, int wz, int dy,
                         int dz) {
             const uint32_t gs = p.start[row + ca], ge = p.start[row + cb + 1];

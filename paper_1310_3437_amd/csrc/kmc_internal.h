@@ -20,6 +20,10 @@ constexpr int kHistLanes = 64;
 constexpr int kSlots = 8;
 // Table stride of the per-kind-pair tables (= KMC_MAX_SPECIES).
 constexpr int kMaxKinds = 8;
+// FP32 screen: thresholds per box for search groups of at most 64, 256, 1024
+// and 4096 cells along x (a group uses the smallest class that holds it;
+// wider rows are split into groups of 4096 cells).
+constexpr int kSpanClasses = 4;
 
 // Device copy of one box.  All derived scalars are computed once on the host
 // (L = hi - lo, R2 = R*R) so that every kernel sees the same bits.  With
@@ -97,7 +101,7 @@ struct Plan {
     P64* B;                        // cell-sorted copy of the current state (records)
     float* vmax_part;              // per scatter block: max |v_k| of its particles this step
     unsigned int* box_vmax;        // per box: max |fl32(v_k)| this step (FP32 bits)
-    ScreenBounds* box_sb;          // per box: FP32 screen thresholds this step
+    ScreenBounds* box_sb;          // per box [kSpanClasses]: FP32 screen thresholds this step
     uint32_t* idA;
     uint32_t* idB;
     uint32_t* cell;                // per particle in A order: global cell
@@ -135,8 +139,8 @@ struct Plan {
     uint8_t* spB;                  // per sorted particle: its kind
     const double* sp_D2;           // [kMaxKinds][kMaxKinds]: (radius_s + radius_t)^2
     const double* sp_mass;         // [kMaxKinds]
-    float* box_kD2;                // per box [kMaxKinds][kMaxKinds]: the FP32 screen's folded
-                                   // D2 constant of each pair of kinds this step
+    float* box_kD2;                // per box [kSpanClasses][kMaxKinds][kMaxKinds]: the FP32
+                                   // screen's folded D2 constant of each pair of kinds this step
 };
 
 // Kernel launchers (kmc_device.hip).  `ev`, when not null, points to

@@ -146,10 +146,14 @@ def adversarial_sparse_row(seed=0, spacing=200, nx=30000, kinds=("radius", "tend
 
 
 @pytest.mark.parametrize("mode", ["half", "full"])
-def test_screen_exact_on_a_sparse_row(kmc, mode):
-    w = adversarial_sparse_row(seed=13)
+@pytest.mark.parametrize("spacing", [6, 30, 200])
+def test_screen_exact_on_a_sparse_row(kmc, mode, spacing):
+    """A wave's lanes span about 190, 930 or 6200 cells: the screen's
+    thresholds for groups of up to 256, 1024 and 4096 cells (the widest
+    rows split into groups of 4096)."""
+    w = adversarial_sparse_row(seed=13, spacing=spacing, nx=150 * spacing)
     sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
-    print(f"\n[screen] sparse row N={w.n} search={mode}", flush=True)
+    print(f"\n[screen] sparse row, a pair every {spacing} cells, N={w.n} search={mode}", flush=True)
     mism64, st64, s64 = gpu_vs_oracle(kmc, w, kmc.KMC_FP64, steps=2, search_mode=sm)
     assert mism64 == 0 and st64
     mism, same, stats = gpu_vs_oracle(kmc, w, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
