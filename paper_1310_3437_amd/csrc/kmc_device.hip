@@ -646,44 +646,6 @@ __device__ __forceinline__ double pair_D2(const Plan& p, const BoxDev& B, uint32
     return p.nspecies ? p.sp_D2[row_i + p.spB[j]] : B.D2;
 }
 
-// Exact FP64 search of one particle over its full 27-cell neighbourhood,
-// straight from the sorted records (rechecks, list overflow, fallback).
-__device__ int32_t search_one64(const Plan& p, uint32_t i)
-{
-    if (p.idB[i] & kGone) return -1;
-    const BoxDev& B = box_of(p, i);
-    const P64* __restrict__ X = p.B;
-    const P64 me = X[i];
-    const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
-    const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
-    const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
-    const double dt = B.dt;
-    const uint32_t row = kind_row(p, i);
-    double best_key = __builtin_inf();
-    uint32_t best_id = 0xFFFFFFFFu;
-    int32_t best = -1;
-    for_each_range(B, cx, cy, cz, p.start, [&](uint32_t s, uint32_t e, int wx, int wy, int wz) {
-        const bool shift = (wx | wy | wz) != 0;
-        const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
-        for (uint32_t j = s; j < e; ++j) {
-            const P64 q = X[j];
-            double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
-            if (shift) { rx = rx + sx; ry = ry + sy; rz = rz + sz; }
-            const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-            if (accept(pq, pair_D2(p, B, row, j), dt)) {   // the particle itself has g2 = 0 and is never accepted
-                const double key = pq.c2 / pq.g2;
-                const uint32_t idj = p.idB[j];
-                if (key < best_key || (key == best_key && idj < best_id)) {
-                    best_key = key;
-                    best_id = idj;
-                    best = (int32_t)j;
-                }
-            }
-        }
-    });
-    return best;
-}
-
 // Relative position of candidate j seen from i in FP64 with the image fixed
 // by the two cells, exactly as in the search.
 __device__ __forceinline__ void rel64(const BoxDev& B, const P64& me, const P64& q, double r[3])
@@ -745,7 +707,8 @@ __device__ __forceinline__ uint32_t wcode(int wx, int wy, int wz)
 struct Found {
     uint32_t* sj; // this lane's kept indices in LDS: pair k at sj[64 k] (one store per pair
                   // instead of a select over register slots)
-    uint32_t w;   // image shift of pair k in bits 6k..6k+5: (wx+1) | (wy+1) << 2 | (wz+1) << 4
+    uint32_t w;   // image shift of pair k in bits 6k..6k+5: (wx+1) | (wy+1) << 2 | (wz+1) << 4;
+                  // bit 31: the overflow pair list was full, nothing more is recorded
     uint32_t sh;  // 6 n
     int n;
     __device__ __forceinline__ void add(const Plan& p, uint32_t i, uint32_t jj, uint32_t wcode)
@@ -755,10 +718,17 @@ struct Found {
             w |= wcode << sh;
             sh += 6u;
             ++n;
-        } else {
+        } else if (!(w >> 31)) {
             const uint32_t idx = atomicAdd(&p.ctl->ovf_count, 1u);
-            if (idx < p.ovf_cap) p.ovf[idx] = make_uint2(i, jj);
-            else atomicOr(&p.ctl->overflow, 1u);
+            if (idx < p.ovf_cap) {
+                p.ovf[idx] = make_uint2(i, jj);
+            } else {
+                // list full: the whole-step FP64 search decides this step, so
+                // the lane records nothing more (the top bit of w, which the
+                // image shifts of kReg pairs leave free, marks it)
+                atomicOr(&p.ctl->overflow, 1u);
+                w |= 0x80000000u;
+            }
         }
     }
     // Decide the kept pairs exactly in FP64 (the FP32 screen keeps pairs it
@@ -1393,14 +1363,13 @@ void k_search_half(Plan p)
 // every pair twice but records nothing, so it suits dense cells with many
 // acceptable partners per particle, where the candidate lists of the
 // half-neighbourhood search overflow.  Rows and staging as in k_search_half.
-template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
-void k_search_full(Plan p)
+// One tile of 64 cell-sorted particles (one wave), writing their partners;
+// STATS: count the pairs for the statistics.
+template <class Pol, bool STATS>
+__device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, typename Pol::Lds& lds, uint32_t* lid)
 {
-    __shared__ typename Pol::Lds lds;
-    __shared__ uint32_t lid[Pol::W];
     const int lane = threadIdx.x;
-    const uint32_t i = xcd_tile(blockIdx.x, gridDim.x) * 64u + (uint32_t)lane;
+    const uint32_t i = tile * 64u + (uint32_t)lane;
     const bool valid = i < p.N;
     const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
@@ -1488,11 +1457,40 @@ void k_search_full(Plan p)
         }
     }
     if (valid) p.partner[i] = best.j;
-    // statistics: pairs accepted (FP64) or decided in FP64 (FP32 screen)
-    uint64_t c = Pol::kScreen ? best.screened : best.accepted;
+    if (STATS) {
+        // statistics: pairs accepted (FP64) or decided in FP64 (FP32 screen)
+        uint64_t c = Pol::kScreen ? best.screened : best.accepted;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c);
+        for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+        if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c);
+    }
+}
+
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
+void k_search_full(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    __shared__ uint32_t lid[Pol::W];
+    search_full_tile<Pol, true>(p, xcd_tile(blockIdx.x, gridDim.x), lds, lid);
+}
+
+// Whole-step FP64 search, by the full-neighbourhood organisation, when a
+// list overflowed (recheck list or overflow pair list) or, under the FP32
+// screen, a particle lies outside its box's grid or a box's scales leave the
+// screen's safe range.  A fixed grid of waves that exits at once unless the
+// step's flag is set, and otherwise takes the tiles in turn.
+constexpr uint32_t kFallbackBlocks = 4096;
+
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
+void k_fallback_full(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    __shared__ uint32_t lid[Pol::W];
+    if (p.ctl->overflow == 0u) return;
+    const uint32_t ntiles = (p.N + 63u) / 64u;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) search_full_tile<Pol, false>(p, t, lds, lid);
 }
 
 // Pairs beyond a search lane's register slots: decided in FP64 and posted to
@@ -1618,6 +1616,7 @@ __device__ int32_t search_one64_wave(const Plan& p, uint32_t i)
 // wave per particle.
 __global__ void k_recheck64(Plan p)
 {
+    if (p.ctl->overflow != 0u) return;   // the whole-step FP64 search follows
     const uint32_t cnt = p.ctl->recheck_count;
     const uint32_t n = cnt < p.recheck_cap ? cnt : p.recheck_cap;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1627,17 +1626,6 @@ __global__ void k_recheck64(Plan p)
         const int32_t b = search_one64_wave(p, i);
         if ((threadIdx.x & 63) == 0) p.partner[i] = b;
     }
-}
-
-// Whole-step FP64 search when the recheck list or the overflow pair list
-// overflowed, or, under the FP32 screen, a particle lies outside its box's
-// grid or a box's scales leave the screen's safe range (exits at once
-// otherwise).
-__global__ void k_fallback64(Plan p)
-{
-    if (p.ctl->overflow == 0u) return;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.N; i += gridDim.x * blockDim.x)
-        p.partner[i] = search_one64(p, i);
 }
 
 // --------------------------------------------------------------------------
@@ -1913,7 +1901,10 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     mark(KMC_PHASE_RECHECK);
     if (p.N > 0 && !full) k_recheck64<<<128, 256, 0, s>>>(p);
     // (the full search raises no overflow; the FP32 sorted copy may)
-    if (p.N > 0 && (!full || p.precision == KMC_FP32_SCREEN)) k_fallback64<<<512, 256, 0, s>>>(p);
+    if (p.N > 0 && (!full || p.precision == KMC_FP32_SCREEN)) {
+        if (p.nspecies > 0) k_fallback_full<PolF64<true>><<<kFallbackBlocks, 64, 0, s>>>(p);
+        else k_fallback_full<PolF64<false>><<<kFallbackBlocks, 64, 0, s>>>(p);
+    }
     mark(KMC_PHASE_RESOLVE);
     if (p.N > 0) {
         if (p.nspecies > 0) k_resolve<true><<<gN, b, 0, s>>>(p);

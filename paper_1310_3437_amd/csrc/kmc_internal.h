@@ -70,12 +70,12 @@ struct alignas(16) SlotEntry {
 struct Ctl {
     unsigned long long step;            // global index of the next step
     unsigned long long steps_done;      // steps completed since init
-    unsigned long long rechecks_total;  // FP32 screen: particles re-searched
-    unsigned long long fallbacks_total; // FP32 screen: list overflows
+    unsigned long long rechecks_total;  // particles re-searched in full FP64 (list overflow)
+    unsigned long long fallbacks_total; // steps that took the whole-step FP64 search
     unsigned long long scratch;         // target of host-requested reductions
     unsigned long long absorbed_total;  // particles absorbed by absorbing faces so far
     unsigned int recheck_count;         // this step's recheck list length
-    unsigned int overflow;              // this step's overflow flag
+    unsigned int overflow;              // this step's flag for the whole-step FP64 search
     unsigned int ovf_count;             // this step's overflow pair list length
     unsigned int pad_[3];
 };
