@@ -482,14 +482,22 @@ __global__ void k_scatter(Plan p)
         if (F32) {
             vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
             // The screen's error bounds take every particle to lie inside the
-            // cell it is binned in.  A particle outside its box's grid (placed
-            // there, or moved more than a box length in one step) is binned in
-            // an end cell; the step's partners then come from the whole-step
-            // FP64 search instead.
+            // cell it is binned in (up to a slack of 1e-9 of a cell edge).  A
+            // particle outside its box's grid (placed there, or moved more
+            // than a box length in one step) is binned in an end cell; the
+            // step's partners then come from the whole-step FP64 search
+            // instead.  Rounding-level excursions (a sphere's mirror image
+            // just past a face of a grid that fits it exactly) stay within
+            // the slack and are ignored.
             if (!(id & kGone)) {
                 const BoxDev& B = box_of(p, i);
                 outside = !(r.x >= B.lo[0] && r.x <= B.hi[0] && r.y >= B.lo[1] && r.y <= B.hi[1] &&
                             r.z >= B.lo[2] && r.z <= B.hi[2]);
+                if (outside) {
+                    const double t0 = 1e-11 * B.h[0], t1 = 1e-11 * B.h[1], t2 = 1e-11 * B.h[2];
+                    outside = !(r.x >= B.lo[0] - t0 && r.x <= B.hi[0] + t0 && r.y >= B.lo[1] - t1 &&
+                                r.y <= B.hi[1] + t1 && r.z >= B.lo[2] - t2 && r.z <= B.hi[2] + t2);
+                }
             }
         }
     }

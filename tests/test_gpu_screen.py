@@ -206,6 +206,25 @@ def scaled(w, pos=1.0, vel=1.0):
 
 
 @pytest.mark.parametrize("mode", ["half", "full"])
+def test_rounding_level_excursions_take_no_fallback(kmc, mode):
+    """Particles one ulp beyond lo or hi (as a mirror image can land) stay
+    within the bounds' slack: the FP32 path keeps the screen and is exact."""
+    w = adversarial(seed=21, kinds=("radius", "tend", "tzero"))
+    s = w.state.copy()
+    b = w.boxes[0]
+    rng = np.random.default_rng(21)
+    pick = rng.choice(w.n, 60, replace=False)
+    for k, i in enumerate(pick):
+        ax = k % 3
+        s[ax, i] = np.nextafter(b.hi[ax], np.inf) if k % 2 else np.nextafter(b.lo[ax], -np.inf)
+    w2 = I.Workload("adversarial_ulp", [b], s, w.seed)
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    mism, same, stats = gpu_vs_oracle(kmc, w2, kmc.KMC_FP32_SCREEN, steps=2, search_mode=sm)
+    print(f"\n[screen] one ulp outside ({mode}): mismatches={mism} fallbacks={stats['fallbacks']}", flush=True)
+    assert mism == 0 and same and stats["fallbacks"] == 0
+
+
+@pytest.mark.parametrize("mode", ["half", "full"])
 @pytest.mark.parametrize("units", [dict(pos=2.0 ** -50), dict(vel=2.0 ** 70)], ids=["tiny_lengths", "huge_speeds"])
 def test_screen_exact_outside_its_safe_range(kmc, units, mode):
     """Cell edges below 2^-40 (FP32 thresholds would underflow) or speeds
