@@ -226,7 +226,10 @@ typedef struct kmc_stats {
     uint64_t steps;            /* steps run since kmc_init                              */
     uint64_t n_total;          /* particles over all boxes                              */
     uint64_t cells_total;      /* cells over all boxes                                  */
-    uint64_t rechecks;         /* particles re-searched in full FP64 (sum over steps)   */
+    uint64_t rechecks;         /* particles listed for a full FP64 re-search (more list
+                                  entries than slots), summed over steps; in a step
+                                  that takes the whole-step FP64 search they are
+                                  covered by it                                         */
     uint64_t fallbacks;        /* steps that took the whole-step FP64 search (a list
                                   overflowed, or the FP32 screen's assumptions failed)  */
     double ms[8];              /* accumulated milliseconds per phase (profile mode)      */
