@@ -1677,8 +1677,13 @@ __device__ __forceinline__ void apply_bc(const BoxDev& B, double x[3], double v[
 }
 
 // K: particles of several kinds (masses from the kind table).
+// One kind of particle: compiled for eight waves per SIMD.  The collision
+// path is bound by the latency of its partner-record gathers, and the
+// default allocation (103 SGPRs) allowed seven; the few scalar values that
+// no longer fit go to vector-register lanes (measured 4.36 -> 3.92 ms at
+// N = 1e8).  With kinds, eight waves would spill vector registers.
 template <bool K>
-__global__ __launch_bounds__(1024) void k_resolve(Plan p)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(K ? 1 : 8))) void k_resolve(Plan p)
 {
     __shared__ uint64_t lds[32];
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
