@@ -240,8 +240,8 @@ def main():
                     help="also run a plain 2 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        print(f"bench.py: the collision step runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
