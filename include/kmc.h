@@ -10,16 +10,18 @@
  *      with r = x_j - x_i, g = v_j - v_i the relative path r + g t comes
  *      closest at t* = -r.g/|g|^2 with squared distance |r x g|^2/|g|^2;
  *      j is acceptable if 0 <= t* <= dt and that distance is below
- *      D = sqrt(sigma/pi); the closest acceptable partner wins, equal
+ *      D = sqrt(sigma/pi) (for particles of several kinds, the sum of the
+ *      two effective radii); the closest acceptable partner wins, equal
  *      distances going to the smaller id;
  *   3. two particles collide only if each chose the other;
  *   4. a colliding pair moves to t*, scatters elastically and isotropically
  *      in its centre-of-mass frame (direction from Philox4x64-10 keyed by
- *      the seed, the step and the pair's smaller id), and moves on with the
- *      new velocities for dt - t*; everybody else streams freely for dt;
- *   5. boundary conditions: periodic or reflecting box faces (Section 1
- *      names reflective, absorptive and periodic boxes) or a reflecting
- *      sphere.
+ *      the seed, the step and the pair's smaller id; mass-weighted for
+ *      particles of unequal masses), and moves on with the new velocities
+ *      for dt - t*; everybody else streams freely for dt;
+ *   5. boundary conditions: periodic, reflecting or absorbing box faces
+ *      (Section 1 names reflective, absorptive and periodic boxes) or a
+ *      reflecting sphere.
  * The exact arithmetic (rounding order, fused operations, random-number
  * layout) is the library's published definition, identical to that of the
  * independent CPU reference it is tested against.
