@@ -49,7 +49,7 @@ def mutual_pairs(p):
     return a, p[a].astype(np.int64), mutual
 
 
-def run_sampled(kmc, w, precision, nsample, seed=0, wall_band=None, **cfg):
+def run_sampled(kmc, w, precision, nsample, seed=0, wall_band=None, kinds=None, **cfg):
     """One GPU step of a single-box workload, checked over all particles by
     properties and at sampled particles against the oracle's per-particle
     evaluation.  Returns (partner array, state) of the GPU run."""
@@ -59,7 +59,7 @@ def run_sampled(kmc, w, precision, nsample, seed=0, wall_band=None, **cfg):
     n = w.n
     print(f"\n[full] {w.name} N={n} precision={precision} cfg={cfg}", flush=True)
     sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics,
-                  precision=precision, **cfg)
+                  precision=precision, kinds=kinds, **cfg)
     sim.step(1)
     p = sim.partners().cpu().numpy()
     st = sim.state()
@@ -83,7 +83,7 @@ def run_sampled(kmc, w, precision, nsample, seed=0, wall_band=None, **cfg):
     sel = np.unique(np.concatenate(parts)).astype(np.int64)
     got = st[:, torch.as_tensor(sel, device=st.device)].cpu().numpy()
     ref_p, ref_s = O.step_sampled(box, w.state, np.arange(n, dtype=np.uint32), 0, sel,
-                                  seed=w.seed, kinematics=w.kinematics)
+                                  seed=w.seed, kinematics=w.kinematics, kinds=kinds)
     bad = np.flatnonzero(p[sel] != ref_p)
     assert bad.size == 0, f"{bad.size} of {sel.size} sampled partners differ, first ids {sel[bad[:5]]}"
     assert np.array_equal(got, ref_s), "sampled post-step states differ"
@@ -104,6 +104,19 @@ def test_c3_sphere_1e8_sampled_and_paths_identical(kmc):
     bench_cfg = dict(history=64, profile=True)
     p32, s32 = run_sampled(kmc, w, kmc.KMC_FP32_SCREEN, 3000, seed=1, wall_band=near_wall, **bench_cfg)
     p64, s64 = run_sampled(kmc, w, kmc.KMC_FP64, 1000, seed=2, **bench_cfg)
+    assert np.array_equal(p32, p64), "FP32-screen and FP64 partner arrays differ"
+    assert bool((s32 == s64).all().item()), "FP32-screen and FP64 states differ"
+
+
+@pytest.mark.timeout(600)
+def test_c6_mixture_1e8_sampled_and_paths_identical(kmc):
+    """Three kinds of particles (radius 1:2:3, mass 1:4:9) at N = 1e8 in the
+    benchmark's launch configuration."""
+    w = I.c6_mixture(n=100_000_000, steps=1)
+    kinds = (w.species, w.radius, w.mass)
+    bench_cfg = dict(history=64, profile=True)
+    p32, s32 = run_sampled(kmc, w, kmc.KMC_FP32_SCREEN, 2000, seed=3, kinds=kinds, **bench_cfg)
+    p64, s64 = run_sampled(kmc, w, kmc.KMC_FP64, 1000, seed=4, kinds=kinds, **bench_cfg)
     assert np.array_equal(p32, p64), "FP32-screen and FP64 partner arrays differ"
     assert bool((s32 == s64).all().item()), "FP32-screen and FP64 states differ"
 
