@@ -2,11 +2,13 @@
 //
 // Parameter validation, workspace layout, kernel launch plan, optional
 // hipGraph capture of one step, read-back, statistics.  The library never
-// allocates device memory: everything lives in the caller's workspace.
+// allocates device memory: everything lives in the caller's workspace, or,
+// for kmc_init_scratch, in a static per-device array of the library.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -58,6 +60,10 @@ int check_box(const kmc_box& b)
         if (b.bc[k] == KMC_BC_PERIODIC && b.ncell[k] < 3) return KMC_EINVAL;
         if (!std::isfinite(b.lo[k]) || !std::isfinite(b.hi[k]) || !(b.hi[k] > b.lo[k])) return KMC_EINVAL;
         if (!finite_pos(b.inv_h[k])) return KMC_EINVAL;
+        // inv_h must be ncell / (hi - lo) up to its rounding: binning uses
+        // the caller's value, while the FP32 screen's error bounds take the
+        // cell edge (hi - lo) / ncell, so a coarser binning would break them
+        if (std::fabs(b.inv_h[k] * (b.hi[k] - b.lo[k]) / (double)b.ncell[k] - 1.0) > 1e-12) return KMC_EINVAL;
         // the 27-cell neighbourhood must contain every point closer than D
         if (b.inv_h[k] * D > 1.0 + 1e-9) return KMC_EINVAL;
         if (b.geometry == KMC_GEOM_SPHERE) {
@@ -261,6 +267,34 @@ void fill_box_dev(BoxDev& d, const kmc_box& b, uint32_t coff, uint32_t poff)
 
 int dev_err(hipError_t e) { return e == hipSuccess ? KMC_OK : KMC_EDEVICE; }
 
+}  // namespace
+
+// Workspace of kmc_init_scratch: one copy per GPU, resident until the process
+// ends.  In host code its name is only a handle: the device address comes
+// from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[KMC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array.
+int scratch_of_current_device(void** out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KMC_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return KMC_EDEVICE;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return KMC_OK;
+}
+
 void fold_events(kmc_ctx* c)
 {
     for (auto& set : c->ev_pending) {
@@ -377,6 +411,22 @@ int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const
     if (bad_kinds != 0) { delete c; return KMC_EINVAL; }
     *out = c;
     return KMC_OK;
+}
+
+int kmc_init_scratch(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,
+                     void* stream, kmc_ctx** out)
+{
+    if (!out) return KMC_EINVAL;
+    *out = nullptr;
+    Totals t;
+    int rc = validate(boxes, nboxes, cfg, t);
+    if (rc != KMC_OK) return rc;
+    Plan probe;
+    if (layout(probe, nullptr, nboxes, *cfg, t) > KMC_SCRATCH_BYTES) return KMC_ENOMEM;
+    void* ws = nullptr;
+    rc = scratch_of_current_device(&ws);
+    if (rc != KMC_OK) return rc;
+    return kmc_init(boxes, nboxes, cfg, d_state, ws, KMC_SCRATCH_BYTES, stream, out);
 }
 
 int kmc_step(kmc_ctx* c, uint32_t nsteps, void* stream)

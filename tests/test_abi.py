@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1310_3437_amd import inputs as I
@@ -26,7 +27,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(kmc.EXPORTS)
-    assert L.kmc_abi_version() == 3
+    assert L.kmc_abi_version() == 4
 
 
 def test_one_hip_runtime_whatever_the_import_order():
@@ -94,6 +95,26 @@ def test_invalid_boxes_rejected(mutate):
     assert _ws([b])[0] == 0
     mutate(b)
     assert _ws([b])[0] == kmc.KMC_EINVAL
+
+
+@pytest.mark.parametrize("scale", [0.5, 1.0 - 1e-9, 1.0 + 1e-9, 2.0])
+def test_inv_h_must_match_the_grid(scale):
+    """inv_h is the caller's, but it must be ncell / (hi - lo) up to
+    rounding on every axis: binning with another value would make bins of a
+    width the FP32 screen's error bounds do not describe."""
+    arr = kmc.make_boxes([_good()])
+    c = kmc.make_config(precision=kmc.KMC_FP32_SCREEN)
+    n = C.c_size_t(0)
+    L = kmc.load()
+    assert L.kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == 0
+    for k in range(3):
+        arr = kmc.make_boxes([_good()])
+        arr[0].inv_h[k] = arr[0].inv_h[k] * scale
+        assert L.kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
+    # one rounding of ncell / (hi - lo) away is accepted
+    arr = kmc.make_boxes([_good()])
+    arr[0].inv_h[0] = float(np.nextafter(arr[0].inv_h[0], np.inf))
+    assert L.kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == 0
 
 
 @pytest.mark.parametrize("cfg", [
@@ -187,3 +208,21 @@ def test_species_workspace_and_validation():
         assert _ws([_good()], species=bad)[0] == kmc.KMC_EINVAL
     # the box's own D2 is still validated, the pair table decides the cell check
     assert _ws([_good()], species=_species(radius=(0.05, 0.125)))[0] == 0
+
+
+def test_scratch_entry_point_rejects_oversized_boxes_before_any_device_work():
+    """kmc_init_scratch sizes the boxes against KMC_SCRATCH_BYTES first: too
+    large a workspace returns KMC_ENOMEM (no device is touched), invalid
+    boxes KMC_EINVAL."""
+    L = kmc.load()
+    big = I.Box(n=1_000_000, lo=(0, 0, 0), hi=(1, 1, 1), ncell=(100, 100, 100), periodic=(True,) * 3,
+                D2=1e-4, dt=1e-3)
+    assert _ws([big])[1] > kmc.KMC_SCRATCH_BYTES
+    ctx = C.c_void_p(0)
+    cfg = kmc.make_config()
+    assert L.kmc_init_scratch(kmc.make_boxes([big]), 1, C.byref(cfg), None, None, C.byref(ctx)) == kmc.KMC_ENOMEM
+    bad = _good()
+    bad.D2 = 0.0
+    assert L.kmc_init_scratch(kmc.make_boxes([bad]), 1, C.byref(cfg), None, None, C.byref(ctx)) == kmc.KMC_EINVAL
+    assert L.kmc_init_scratch(kmc.make_boxes([_good()]), 1, C.byref(cfg), None, None, None) == kmc.KMC_EINVAL
+    assert not ctx.value

@@ -83,6 +83,67 @@ def test_direction_depends_on_seed_step_and_id():
     assert np.array_equal(a, O.direction(1, 0, 5))
 
 
+def _numpy_philox_block(ctr, key):
+    """One Philox4x64-10 block from numpy's bit generator (black box; its
+    first block is produced at counter + 1, a 256-bit add)."""
+    c = ctr[0] | (ctr[1] << 64) | (ctr[2] << 128) | (ctr[3] << 192)
+    c = (c - 1) % (1 << 256)
+    npc = [(c >> (64 * k)) & MASK64 for k in range(4)]
+    g = np.random.Philox(key=np.array(key, dtype=np.uint64), counter=np.array(npc, dtype=np.uint64))
+    return [int(x) for x in g.random_raw(4)]
+
+
+@pytest.mark.parametrize("seed,step,a", [
+    (1, 0, 0), (1, 0, 1), (1, 7, 12345), (2, 3, 99),
+    (0xDEADBEEFCAFEBABE, 5, 2 ** 31 - 2), (77, 10 ** 12, 2 ** 31 - 1), (3, 2 ** 40 + 5, 2 ** 30 + 17),
+])
+def test_direction_from_numpy_philox_bit_exact(seed, step, a):
+    """The 3-D scatter direction recomputed from numpy's Philox words: key
+    (seed, 0), block k at counter (k, a, step, 0), candidate points from words
+    (0, 1) then (2, 3), e = 2 (w >> 11) 2^-53 - 1, the first point with
+    0 < s = e1 e1 + e2 e2 < 1 gives n = (2 e1 sqrt(1 - s), 2 e2 sqrt(1 - s),
+    1 - 2 s) (Marsaglia 1972).  Python floats are binary64 with correctly
+    rounded sqrt, so the result must equal the oracle bit for bit; a swapped
+    word, another counter layout or a sign slip in any component fails."""
+    want = None
+    for blk in range(32):
+        w = _numpy_philox_block((blk, a, step, 0), (seed, 0))
+        for t in range(2):
+            e1 = 2.0 * ((w[2 * t] >> 11) * 2.0 ** -53) - 1.0
+            e2 = 2.0 * ((w[2 * t + 1] >> 11) * 2.0 ** -53) - 1.0
+            s = e1 * e1 + e2 * e2
+            if 0.0 < s < 1.0:
+                f = 2.0 * math.sqrt(1.0 - s)
+                want = (e1 * f, e2 * f, 1.0 - 2.0 * s)
+                break
+        if want:
+            break
+    got = O.direction(seed, step, a)
+    assert [float(x).hex() for x in got] == [x.hex() for x in want]
+
+
+def test_direction_rejects_points_outside_the_disk():
+    """Some (seed, step, a) have their first candidate point outside the unit
+    disk; the direction must then come from the second (or a later) point,
+    recomputed here from numpy's Philox words."""
+    seen = 0
+    for a in range(400):
+        w = _numpy_philox_block((0, a, 9, 0), (5, 0))
+        e1 = 2.0 * ((w[0] >> 11) * 2.0 ** -53) - 1.0
+        e2 = 2.0 * ((w[1] >> 11) * 2.0 ** -53) - 1.0
+        if e1 * e1 + e2 * e2 < 1.0:
+            continue
+        seen += 1
+        e1 = 2.0 * ((w[2] >> 11) * 2.0 ** -53) - 1.0
+        e2 = 2.0 * ((w[3] >> 11) * 2.0 ** -53) - 1.0
+        s = e1 * e1 + e2 * e2
+        if not 0.0 < s < 1.0:
+            continue
+        f = 2.0 * math.sqrt(1.0 - s)
+        assert list(O.direction(5, 9, a)) == [e1 * f, e2 * f, 1.0 - 2.0 * s]
+    assert seen > 50      # about 21% of first points fall outside the disk
+
+
 def test_pair_hash_is_splitmix64():
     # SplitMix64 from state 0: first output (published test vector)
     assert O.pair_hash(0, 0) == 0xE220A8397B1DCDAF
@@ -276,6 +337,71 @@ def test_particles_outside_the_grid_bin_in_the_end_cells(periodic):
         pc, _ = O.find_partners(box, s, ids, nthreads=4)
         pb, _ = O.find_partners(box, s, ids, brute=True)
         assert np.array_equal(pc, pb), f"trial {trial}"
+
+
+def _geometric_partners(s, D2, dt, L, periodic, ids):
+    """All-pairs DCA with no neighbourhood test at all: r by the minimum
+    image on periodic axes, the Lagrange form d_min^2 = |r|^2 - b^2/g2 and
+    t* = -b/g2 in plain numpy float64 (no fused operations).  Returns the
+    partner array and the smallest relative margin of any decision, so a
+    caller can see that no decision lies within rounding of a boundary."""
+    n = s.shape[1]
+    out = np.full(n, -1, dtype=np.int64)
+    margin = np.inf
+    for i in range(n):
+        r = s[0:3] - s[0:3, i:i + 1]
+        if periodic:
+            r = np.where(r > 0.5 * L, r - L, r)
+            r = np.where(r < -0.5 * L, r + L, r)
+        g = s[3:6] - s[3:6, i:i + 1]
+        g2 = (g * g).sum(axis=0)
+        b = (r * g).sum(axis=0)
+        rr = (r * r).sum(axis=0)
+        ok = g2 > 0
+        ok[i] = False
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ts = np.where(ok, -b / g2, np.inf)
+            dm = np.where(ok, rr - b * b / g2, np.inf)
+        acc = ok & (ts >= 0.0) & (ts <= dt) & (dm < D2)
+        near = ok & (dm < 4 * D2) & (ts > -dt) & (ts < 2 * dt)
+        if near.any():
+            m = np.minimum(np.abs(ts[near]) / dt, np.abs(ts[near] - dt) / dt)
+            m = np.minimum(m, np.abs(dm[near] - D2) / D2)
+            margin = min(margin, float(m.min()))
+        if acc.any():
+            cand = np.flatnonzero(acc)
+            order = np.lexsort((ids[cand], dm[cand]))
+            out[i] = cand[order[0]]
+            if len(cand) > 1:
+                k0, k1 = dm[cand[order[0]]], dm[cand[order[1]]]
+                margin = min(margin, abs(k1 - k0) / max(abs(k0), abs(k1), D2))
+    return out, margin
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_cell_list_equals_pure_geometry_when_reach_fits_a_cell(periodic):
+    """With reach = sqrt(D^2 + (g_max dt)^2) <= h every acceptable pair lies in
+    neighbouring cells (|r|^2 = d_min^2 + (|g| t*)^2 <= reach^2), so the
+    neighbourhood test is vacuous: the cell-list search must equal an
+    all-pairs closest-approach search that knows nothing of cells."""
+    rng = np.random.default_rng(4242 if periodic else 2424)
+    tot = 0
+    for trial in range(6):
+        n = int(rng.integers(800, 1500))
+        nc = int(rng.integers(4, 8))
+        h = 1.0 / nc
+        D = h * float(rng.uniform(0.4, 0.9))
+        box, s = _rand_box(rng, n, periodic, nc, D, 1.0)
+        vmax = float(np.sqrt((s[3:6] ** 2).sum(axis=0)).max())
+        dt = 0.999 * math.sqrt(h * h - D * D) / (2.0 * vmax)
+        box.dt = dt
+        ids = rng.permutation(n).astype(np.uint32)
+        pc, _ = O.find_partners(box, s, ids, nthreads=4)
+        pg, margin = _geometric_partners(s, D * D, dt, 1.0, periodic, ids)
+        assert margin > 1e-9, f"trial {trial}: a decision within rounding of a boundary"
+        assert np.array_equal(pc, pg), f"trial {trial}"
+        tot += int((pc >= 0).sum())
+    assert tot > 300      # enough accepted pairs to exercise the argmin
 
 
 def test_search_independent_of_particle_order_and_threads():
