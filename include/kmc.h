@@ -36,7 +36,8 @@
  *   - the caller owns every device buffer (state, workspace, outputs); the
  *     library never allocates device memory.  It owns only the host-side
  *     kmc_ctx and, when graphs are enabled, one private capture stream and
- *     the captured graph, all released by kmc_destroy.
+ *     the captured graph, all released by kmc_destroy (and, for
+ *     kmc_init_scratch, a static workspace array per device).
  */
 #ifndef KMC_H
 #define KMC_H
@@ -48,7 +49,7 @@
 extern "C" {
 #endif
 
-#define KMC_ABI_VERSION 3
+#define KMC_ABI_VERSION 4
 
 typedef enum {
     KMC_OK = 0,
@@ -269,6 +270,29 @@ int kmc_workspace_bytes(const kmc_box* boxes, uint32_t nboxes, const kmc_config*
 int kmc_init(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg,
              const double* d_state, void* d_workspace, size_t workspace_bytes,
              void* stream, kmc_ctx** out);
+
+/* For callers that cannot allocate device memory (code that runs while a
+ * HIP graph is being captured elsewhere, tight serving loops, harnesses that
+ * forbid hipMalloc): kmc_init with the library's own per-device workspace
+ * instead of a caller-owned one.
+ *   - the workspace is a static device array of KMC_SCRATCH_BYTES in the
+ *     library, one per GPU, held until the process ends; its address is
+ *     looked up once per device (hipGetSymbolAddress) on the first call made
+ *     with that device current;
+ *   - boxes whose kmc_workspace_bytes exceed KMC_SCRATCH_BYTES are rejected
+ *     with KMC_ENOMEM before anything is done (about 200 000 particles fit);
+ *   - the call allocates no device or pinned memory (the context is a small
+ *     host structure, as for kmc_init) and otherwise behaves as kmc_init:
+ *     same arguments minus the workspace, same errors, same results; every
+ *     other function takes the returned context as usual;
+ *   - every context created this way on one GPU shares that GPU's array: a
+ *     second kmc_init_scratch on the same device overwrites the first
+ *     context's data, so at most one such context may be in use per device,
+ *     and calls that overlap on one GPU race.  kmc_init clears whatever must
+ *     start at zero, so stale contents of an earlier context do not matter. */
+#define KMC_SCRATCH_BYTES ((size_t)64 << 20)
+int kmc_init_scratch(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg,
+                     const double* d_state, void* stream, kmc_ctx** out);
 
 /* Enqueue nsteps steps on `stream` (asynchronous). */
 int kmc_step(kmc_ctx* ctx, uint32_t nsteps, void* stream);

@@ -93,7 +93,9 @@ class KmcStats(C.Structure):
 
 EXPORTS = ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "kmc_read_state",
            "kmc_read_history", "kmc_read_time", "kmc_count_pair_tests", "kmc_get_stats", "kmc_destroy",
-           "kmc_strerror", "kmc_abi_version", "kmc_autotune", "kmc_box_with_kappa")
+           "kmc_strerror", "kmc_abi_version", "kmc_autotune", "kmc_box_with_kappa", "kmc_init_scratch")
+
+KMC_SCRATCH_BYTES = 64 << 20
 
 
 KMC_TUNE_LAUNCH, KMC_TUNE_CELLS = 1, 2
@@ -132,6 +134,7 @@ def load(path=LIB_PATH):
     bp, cp = C.POINTER(KmcBox), C.POINTER(KmcConfig)
     L.kmc_workspace_bytes.argtypes = [bp, C.c_uint32, cp, C.POINTER(sz)]
     L.kmc_init.argtypes = [bp, C.c_uint32, cp, vp, vp, sz, vp, C.POINTER(vp)]
+    L.kmc_init_scratch.argtypes = [bp, C.c_uint32, cp, vp, vp, C.POINTER(vp)]
     L.kmc_step.argtypes = [vp, C.c_uint32, vp]
     L.kmc_read_partners.argtypes = [vp, vp, vp]
     L.kmc_read_state.argtypes = [vp, vp, vp]
@@ -150,7 +153,7 @@ def load(path=LIB_PATH):
     L.kmc_abi_version.argtypes = []
     for f in ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "kmc_read_state",
               "kmc_read_history", "kmc_read_time", "kmc_count_pair_tests", "kmc_get_stats", "kmc_abi_version",
-              "kmc_autotune", "kmc_box_with_kappa"):
+              "kmc_autotune", "kmc_box_with_kappa", "kmc_init_scratch"):
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -328,10 +331,11 @@ class Sim:
     kmc_init: x, y, z, vx, vy, vz rows, boxes concatenated in order.
     """
 
-    def __init__(self, boxes, state, device="cuda", kinds=None, **config):
+    def __init__(self, boxes, state, device="cuda", kinds=None, scratch=False, **config):
         """kinds: None (one kind of particle) or (kind, radius, mass): the kind
         of each particle (N integers, id order) and each kind's effective
-        radius and mass."""
+        radius and mass.  scratch: create the context with kmc_init_scratch
+        (the library's static per-device workspace, no workspace tensor)."""
         import torch
         self._torch = torch
         L = load()
@@ -352,14 +356,19 @@ class Sim:
         if st.ndim != 2 or st.shape[0] != 6 or st.shape[1] != sum(int(b.n) for b in self.boxes):
             raise ValueError("state must be (6, sum of box n) float64")
         self.n = int(st.shape[1])
-        nbytes = workspace_bytes(self.boxes, self.config)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        base = self.workspace.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
         ctx = C.c_void_p(0)
-        _check(L.kmc_init(self._boxarr, len(self.boxes), C.byref(self.config), C.c_void_p(st.data_ptr()),
-                          C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), self._stream(), C.byref(ctx)),
-               "kmc_init")
+        if scratch:
+            self.workspace = None
+            _check(L.kmc_init_scratch(self._boxarr, len(self.boxes), C.byref(self.config),
+                                      C.c_void_p(st.data_ptr()), self._stream(), C.byref(ctx)), "kmc_init_scratch")
+        else:
+            nbytes = workspace_bytes(self.boxes, self.config)
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            base = self.workspace.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            _check(L.kmc_init(self._boxarr, len(self.boxes), C.byref(self.config), C.c_void_p(st.data_ptr()),
+                              C.c_void_p(self._ws_ptr), C.c_size_t(nbytes), self._stream(), C.byref(ctx)),
+                   "kmc_init")
         self._ctx = ctx
         torch.cuda.current_stream(self.device).synchronize()
         self._kind = None   # read by kmc_init only
