@@ -38,6 +38,8 @@ class OrcBox(C.Structure):
         ("species", C.POINTER(C.c_uint8)),
         ("radius", C.POINTER(C.c_double)),
         ("mass", C.POINTER(C.c_double)),
+        ("adapt_levels", C.c_int32),
+        ("adapt_threshold", C.c_int32),
     ]
 
 
@@ -99,12 +101,15 @@ def _ptr(a, ct):
     return a.ctypes.data_as(C.POINTER(ct))
 
 
-def make_box(box, seed=1, kinematics=0, dims=3, kinds=None):
+def make_box(box, seed=1, kinematics=0, dims=3, kinds=None, adapt=(0, 0)):
     """OrcBox from a paper_1310_3437_amd.inputs.Box (or any object with the
     same attributes).  kinds = (species, radius, mass): per-particle kind
     (uint8, the box's particles) and per-kind effective radius and mass, or
-    None for one kind of particle."""
+    None for one kind of particle.  adapt = (levels, threshold) of the
+    density-adaptive bins ((0, 0): the uniform grid)."""
     ob = OrcBox()
+    ob.adapt_levels = int(adapt[0])
+    ob.adapt_threshold = int(adapt[1])
     if kinds is not None:
         sp, rad, mass = kinds
         sp = np.ascontiguousarray(sp, dtype=np.uint8)
@@ -159,13 +164,13 @@ def pair(box, pi, pj, wrap=(0, 0, 0)):
     return dict(r=tuple(q.r), g=tuple(q.g), b=q.b, g2=q.g2, c2=q.c2, key=q.key, acc=bool(q.acc))
 
 
-def find_partners(box, state, ids=None, nthreads=0, brute=False, kinds=None):
+def find_partners(box, state, ids=None, nthreads=0, brute=False, kinds=None, adapt=(0, 0)):
     """Partner array (indices into the box's particles, -1 for none)."""
     s = _soa(state)
     n = s.shape[1]
     ids = np.arange(n, dtype=np.uint32) if ids is None else np.ascontiguousarray(ids, dtype=np.uint32)
     out = np.empty(n, dtype=np.int32)
-    ob = make_box(box, kinds=kinds)
+    ob = make_box(box, kinds=kinds, adapt=adapt)
     ob.n = n
     if brute:
         rc = lib().orc_find_partners_bruteforce(C.byref(ob), _ptr(s, C.c_double), _ptr(ids, C.c_uint32),
@@ -230,7 +235,7 @@ def adaptive_dt(box, state, factor=1.0, gone=None):
     return float(out.value)
 
 
-def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, dims=3, kinds=None):
+def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, dims=3, kinds=None, adapt=(0, 0)):
     """The oracle step of one box evaluated at the particles `sel` only
     (indices into the box); `state` is not modified.  Returns (partner
     indices of the selected particles, their (6, len(sel)) post-step state)."""
@@ -238,7 +243,7 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, d
     n = s.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     sel = np.ascontiguousarray(sel, dtype=np.int64)
-    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds, adapt=adapt)
     ob.n = n
     partner = np.empty(len(sel), dtype=np.int32)
     out = np.empty((len(sel), 6), dtype=np.float64)
@@ -250,7 +255,7 @@ def step_sampled(box, state, ids, step, sel, seed=1, kinematics=0, nthreads=0, d
     return partner, out.T.copy()
 
 
-def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, gone=None, kinds=None):
+def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, gone=None, kinds=None, adapt=(0, 0)):
     """One oracle step of one box, in place on `state` ((6, n) float64,
     C-contiguous) and on `gone` (uint8 per particle, 1 = absorbed; required
     with absorbing faces).  kinds as in make_box.  Returns (partner indices,
@@ -258,7 +263,7 @@ def step_box(box, state, ids, step, seed=1, kinematics=0, nthreads=0, dims=3, go
     assert state.dtype == np.float64 and state.flags.c_contiguous and state.shape[0] == 6
     n = state.shape[1]
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
-    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds)
+    ob = make_box(box, seed=seed, kinematics=kinematics, dims=dims, kinds=kinds, adapt=adapt)
     ob.n = n
     partner = np.empty(n, dtype=np.int32)
     npairs = C.c_uint64(0)
@@ -310,7 +315,9 @@ class Run:
             p, npairs, dig, t = step_box(box, self.state[b], self.ids[b], self.step_index,
                                          seed=self.w.seed, kinematics=self.w.kinematics,
                                          dims=getattr(self.w, "dims", 3), gone=self.gone[b],
-                                         nthreads=self.nthreads, kinds=self.kinds(b))
+                                         nthreads=self.nthreads, kinds=self.kinds(b),
+                                         adapt=(getattr(self.w, "adapt_levels", 0),
+                                                getattr(self.w, "adapt_threshold", 0)))
             ids = self.ids[b]
             has = p >= 0
             pb[ids[has]] = ids[p[has]]

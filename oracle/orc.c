@@ -42,6 +42,12 @@ static int box_ok(const orc_box* b)
     for (int k = 0; k < 3; ++k)
         if (b->absorb[k] && (b->periodic[k] || b->sphere)) return 0;
     if (b->nspecies < 0 || b->nspecies > 8) return 0;
+    if (b->adapt_levels < 0 || b->adapt_levels > 3 || b->adapt_threshold < 0) return 0;
+    if (b->adapt_levels > 0) {
+        if (b->dims == 2) return 0;   /* bins are split in all three axes */
+        for (int k = 0; k < 3; ++k)
+            if (b->ncell[k] > (1 << 27)) return 0;   /* finest index fits int32 */
+    }
     if (b->nspecies > 0) {
         if (!b->radius || !b->mass || (b->n > 0 && !b->species)) return 0;
         for (int s = 0; s < b->nspecies; ++s)
@@ -156,11 +162,38 @@ typedef struct {
     int64_t ncells;
     int64_t* start;   /* ncells + 1 */
     int64_t* member;  /* n: particle indices grouped by bin, index order within a bin */
+    /* adaptive bins only (NULL otherwise) */
+    int8_t* level;    /* ncells: refinement level of each bin this step */
+    int32_t* fine;    /* 3n: each particle's index on the finest grid */
 } csr_t;
+
+/* Adaptive bins: index of a point on the finest grid along one axis,
+ * clamp(floor((x - lo) * (inv_h * 2^L)), 0, n 2^L - 1).  inv_h * 2^L is exact,
+ * and so the bin of the uniform grid is this index >> L (the power-of-two
+ * scaling commutes with the rounding of the product). */
+static int32_t fine1(double x, double lo, double inv_h, int32_t n, int L)
+{
+    double f = floor((x - lo) * (inv_h * (double)(1 << L)));
+    if (!(f >= 0.0)) return 0;
+    double m = (double)n * (double)(1 << L);
+    if (f >= m) return (int32_t)(m - 1.0);
+    return (int32_t)f;
+}
+
+/* Refinement level of a bin holding `count` particles: the smallest l in
+ * 0..L with count <= threshold * 8^l, else L. */
+static int8_t bin_level(int64_t count, int32_t threshold, int L)
+{
+    for (int l = 0; l < L; ++l)
+        if (count <= (int64_t)threshold << (3 * l)) return (int8_t)l;
+    return (int8_t)L;
+}
 
 static int build_csr(const orc_box* b, const double* s, const unsigned char* gone, csr_t* t)
 {
     int64_t n = b->n;
+    t->level = NULL;
+    t->fine = NULL;
     t->ncells = (int64_t)b->ncell[0] * b->ncell[1] * b->ncell[2];
     t->start = (int64_t*)calloc((size_t)t->ncells + 1, sizeof(int64_t));
     t->member = (int64_t*)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
@@ -169,13 +202,27 @@ static int build_csr(const orc_box* b, const double* s, const unsigned char* gon
         free(t->start); free(t->member); free(cellof);
         return -1;
     }
+    const int L = b->adapt_levels;
+    if (L > 0) {
+        t->fine = (int32_t*)malloc((size_t)(n > 0 ? 3 * n : 1) * sizeof(int32_t));
+        t->level = (int8_t*)malloc((size_t)t->ncells + 1);
+        if (!t->fine || !t->level) {
+            free(t->start); free(t->member); free(cellof); free(t->fine); free(t->level);
+            return -1;
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
         if (gone && gone[i]) { cellof[i] = -1; continue; }   /* in no bin */
         int32_t c[3];
         orc_cell_coords(b, s[i], s[n + i], s[2 * n + i], c);
+        if (L > 0)
+            for (int k = 0; k < 3; ++k) t->fine[3 * i + k] = fine1(s[(int64_t)k * n + i], b->lo[k], b->inv_h[k],
+                                                                  b->ncell[k], L);
         cellof[i] = linear_cell(b, c);
         t->start[cellof[i] + 1] += 1;
     }
+    if (L > 0)
+        for (int64_t c = 0; c < t->ncells; ++c) t->level[c] = bin_level(t->start[c + 1], b->adapt_threshold, L);
     for (int64_t c = 0; c < t->ncells; ++c) t->start[c + 1] += t->start[c];
     int64_t* fill = (int64_t*)malloc((size_t)t->ncells * sizeof(int64_t) + 1);
     if (!fill) {
@@ -194,6 +241,34 @@ static void free_csr(csr_t* t)
 {
     free(t->start);
     free(t->member);
+    free(t->level);
+    free(t->fine);
+}
+
+/* Adaptive bins: the interval [lo, hi] of finest indices that particle i's
+ * leaf spans on each axis. */
+static void leaf_of(const orc_box* b, const csr_t* t, int64_t i, int32_t lo[3], int32_t hi[3])
+{
+    const int L = b->adapt_levels;
+    int32_t c[3];
+    for (int k = 0; k < 3; ++k) c[k] = t->fine[3 * i + k] >> L;
+    const int sh = L - t->level[linear_cell(b, c)];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = (t->fine[3 * i + k] >> sh) << sh;
+        hi[k] = lo[k] + (1 << sh) - 1;
+    }
+}
+
+/* Do two leaves touch, the second seen with the periodic image wrap? */
+static int leaves_touch(const orc_box* b, const int32_t alo[3], const int32_t ahi[3], const int32_t blo[3],
+                        const int32_t bhi[3], const int32_t wrap[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        const int64_t M = (int64_t)b->ncell[k] << b->adapt_levels;
+        const int64_t b0 = blo[k] + wrap[k] * M, b1 = bhi[k] + wrap[k] * M;
+        if (b0 > (int64_t)ahi[k] + 1 || (int64_t)alo[k] > b1 + 1) return 0;
+    }
+    return 1;
 }
 
 int orc_max_threads(void)
@@ -217,6 +292,9 @@ static int64_t search_one(const orc_box* b, const double* s, const uint32_t* ids
     double best_key = INFINITY;
     uint32_t best_id = UINT32_MAX;
     int64_t best = -1;
+    /* adaptive bins: i's leaf; every leaf it touches lies in the 27 bins */
+    int32_t alo[3] = {0, 0, 0}, ahi[3] = {0, 0, 0};
+    if (t->level) leaf_of(b, t, i, alo, ahi);
     for (int dz = -1; dz <= 1; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
             for (int dx = -1; dx <= 1; ++dx) {
@@ -239,6 +317,11 @@ static int64_t search_one(const orc_box* b, const double* s, const uint32_t* ids
                 for (int64_t q = t->start[cell]; q < t->start[cell + 1]; ++q) {
                     int64_t j = t->member[q];
                     if (j == i) continue;
+                    if (t->level) {
+                        int32_t blo[3], bhi[3];
+                        leaf_of(b, t, j, blo, bhi);
+                        if (!leaves_touch(b, alo, ahi, blo, bhi, wrap)) continue;
+                    }
                     ++*tests;
                     load6(s, n, j, pj);
                     orc_pair_q pq;
@@ -325,11 +408,57 @@ static int axis_adjacent(const orc_box* b, int k, int32_t ci, int32_t cj, int32_
     return d >= -1 && d <= 1;
 }
 
+/* Adaptive bins, by brute force: the leaf interval [lo, hi] of a point on
+ * each axis, given the particle counts of every bin. */
+static void bf_leaf(const orc_box* b, const int64_t* count, const double p[6], int32_t lo[3], int32_t hi[3])
+{
+    const int L = b->adapt_levels;
+    int32_t g[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+        g[k] = fine1(p[k], b->lo[k], b->inv_h[k], b->ncell[k], L);
+        c[k] = g[k] >> L;
+    }
+    const int sh = L - bin_level(count[linear_cell(b, c)], b->adapt_threshold, L);
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = (g[k] >> sh) << sh;
+        hi[k] = lo[k] + (1 << sh) - 1;
+    }
+}
+
+/* Two leaf intervals along axis k: do they touch (closed boxes intersect)?
+ * On a periodic axis of M finest bins try the images -M, 0, +M of the
+ * second; *wrap receives the one that touches. */
+static int bf_axis_touch(const orc_box* b, int k, int32_t alo, int32_t ahi, int32_t blo, int32_t bhi, int32_t* wrap)
+{
+    const int64_t M = (int64_t)b->ncell[k] << b->adapt_levels;
+    for (int w = -1; w <= 1; ++w) {
+        if (w != 0 && !b->periodic[k]) continue;
+        const int64_t b0 = blo + w * M, b1 = bhi + w * M;
+        if (b0 <= (int64_t)ahi + 1 && (int64_t)alo <= b1 + 1) {
+            *wrap = w;
+            return 1;
+        }
+    }
+    return 0;
+}
+
 int orc_find_partners_bruteforce(const orc_box* b, const double* s,
                                  const uint32_t* ids, int32_t* partner)
 {
     if (!box_ok(b) || (b->n > 0 && (!s || !ids || !partner))) return -1;
     int64_t n = b->n;
+    int64_t* count = NULL;
+    if (b->adapt_levels > 0) {
+        /* particles per bin of the uniform grid, counted directly */
+        const int64_t nc = (int64_t)b->ncell[0] * b->ncell[1] * b->ncell[2];
+        count = (int64_t*)calloc((size_t)nc, sizeof(int64_t));
+        if (!count) return -2;
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t c[3];
+            orc_cell_coords(b, s[i], s[n + i], s[2 * n + i], c);
+            count[linear_cell(b, c)] += 1;
+        }
+    }
     for (int64_t i = 0; i < n; ++i) {
         double pi[6], pj[6];
         load6(s, n, i, pi);
@@ -344,7 +473,14 @@ int orc_find_partners_bruteforce(const orc_box* b, const double* s,
             int32_t cj[3], wrap[3];
             orc_cell_coords(b, pj[0], pj[1], pj[2], cj);
             int adj = 1;
-            for (int k = 0; k < 3; ++k) adj &= axis_adjacent(b, k, ci[k], cj[k], &wrap[k]);
+            if (count) {
+                int32_t alo[3], ahi[3], blo[3], bhi[3];
+                bf_leaf(b, count, pi, alo, ahi);
+                bf_leaf(b, count, pj, blo, bhi);
+                for (int k = 0; k < 3; ++k) adj &= bf_axis_touch(b, k, alo[k], ahi[k], blo[k], bhi[k], &wrap[k]);
+            } else {
+                for (int k = 0; k < 3; ++k) adj &= axis_adjacent(b, k, ci[k], cj[k], &wrap[k]);
+            }
             if (!adj) continue;
             orc_pair_q pq;
             pair_q(b, pi, pj, wrap, pair_D2(b, i, j), &pq);
@@ -356,6 +492,7 @@ int orc_find_partners_bruteforce(const orc_box* b, const double* s,
         }
         partner[i] = (int32_t)best;
     }
+    free(count);
     return 0;
 }
 

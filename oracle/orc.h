@@ -70,6 +70,23 @@ typedef struct {
     const uint8_t* species; /* n entries when nspecies > 0                     */
     const double*  radius;  /* nspecies entries, > 0                           */
     const double*  mass;    /* nspecies entries, > 0                           */
+    /* Density-adaptive bins (Section 1 proposes an adaptive bin size against
+     * the load imbalance of dense bins; Section 4: areas of higher density
+     * get smaller bins).  adapt_levels == 0: the uniform grid above.
+     * 1 <= adapt_levels <= 3: at the start of the step each bin c of the grid
+     * holding n_c particles is split into 2^l x 2^l x 2^l equal sub-bins,
+     * l the smallest level in 0..adapt_levels with n_c <= adapt_threshold *
+     * 8^l (adapt_levels if none).  A particle's bin (its leaf) is the sub-bin
+     * it falls in; on the finest grid (ncell[k] * 2^adapt_levels bins per
+     * axis, index clamp(floor((x - lo) * (inv_h * 2^adapt_levels)), 0, ..))
+     * a leaf spans an interval of finest indices per axis.  Two particles
+     * are in each other's collision neighbourhood when their leaves touch
+     * (their closed boxes intersect: on every axis the index intervals are at
+     * most one apart, across the seam of a periodic axis with the image that
+     * makes them so, which is unique with >= 3 bins per periodic axis).  On a
+     * uniform grid (no bin split) this is the 27-bin rule. */
+    int32_t  adapt_levels;
+    int32_t  adapt_threshold;
 } orc_box;
 
 /* Quantities of one ordered pair (searcher i, candidate j). */

@@ -76,6 +76,8 @@ class Workload:
     species: np.ndarray = None   # (N,) uint8 kind of each particle (id order), None: one kind
     radius: tuple = ()           # per kind: effective radius (a pair interacts below the sum)
     mass: tuple = ()             # per kind: mass
+    adapt_levels: int = 0        # density-adaptive bins: at most this many halvings of a bin (0: uniform)
+    adapt_threshold: int = 0     # ... a bin is split while it holds more than threshold * 8^level particles
     info: dict = field(default_factory=dict)
 
     @property

@@ -1033,3 +1033,141 @@ def test_kinds_are_validated():
                   (np.zeros(2, np.uint8), (0.01,) * 9, (1.0,) * 9)]:          # more than 8 kinds
         with pytest.raises(ValueError):
             O.find_partners(_kinds_box(2), s, kinds=kinds)
+
+
+# --------------------------------------------------------------------------
+# Density-adaptive bins (Section 1: an adaptive bin size against the load
+# imbalance of dense bins; Section 4: smaller bins where the density is higher)
+# --------------------------------------------------------------------------
+
+def _clustered(rng, n, periodic, nc, D, dt, nclust=3, width=0.02):
+    """Particles in a few tight clusters plus a uniform background, so that
+    bins of every refinement level occur side by side."""
+    box, s = _rand_box(rng, n, periodic, nc, D, dt)
+    k = int(0.6 * n)
+    centres = rng.random((3, nclust))
+    which = rng.integers(0, nclust, k)
+    pts = centres[:, which] + width * rng.standard_normal((3, k))
+    s[0:3, :k] = np.mod(pts, 1.0) if periodic else np.clip(pts, 0.0, 1.0 - 1e-12)
+    s[0:3][s[0:3] >= 1.0] = 0.0
+    return box, s
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_adaptive_bins_cell_list_equals_bruteforce(periodic, levels):
+    """The cell-list search with density-adaptive bins equals a brute force
+    over all pairs that decides the neighbourhood from the two leaves alone
+    (closed boxes of the sub-bins touch, the periodic image tried on a
+    circle), on clustered gases where bins of several levels meet; a third of
+    the trials snap particles onto bin and sub-bin faces."""
+    rng = np.random.default_rng(1000 * levels + periodic)
+    for trial in range(25):
+        n = int(rng.integers(50, 700))
+        nc = int(rng.integers(3, 7))
+        h = 1.0 / nc
+        D = h * float(rng.uniform(0.3, 1.0))
+        dt = float(rng.uniform(0.02, 0.3)) * h
+        box, s = _clustered(rng, n, periodic, nc, D, dt)
+        if trial % 3 == 0:
+            q = rng.random((3, n)) < 0.3
+            f = 1 << levels
+            s[0:3][q] = rng.integers(0, nc * f + 1, q.sum()) * (h / f)
+            s[0:3][s[0:3] >= 1.0] = 0.0 if periodic else 1.0
+        thr = int(rng.integers(0, 12))
+        ids = rng.permutation(n).astype(np.uint32)
+        pc, _ = O.find_partners(box, s, ids, nthreads=4, adapt=(levels, thr))
+        pb, _ = O.find_partners(box, s, ids, brute=True, adapt=(levels, thr))
+        assert np.array_equal(pc, pb), f"trial {trial}"
+
+
+def test_adaptive_bins_unsplit_is_the_uniform_grid():
+    """A threshold no bin exceeds leaves every bin whole: the step equals the
+    uniform-grid step bit for bit."""
+    w = I.c5_blobs(n=20_000, steps=3)
+    ref = O.Run(w)
+    w2 = I.c5_blobs(n=20_000, steps=3)
+    w2.adapt_levels, w2.adapt_threshold = 3, 1 << 24
+    got = O.Run(w2)
+    for _ in range(3):
+        assert ref.step() == got.step()
+        assert np.array_equal(ref.partner_by_id, got.partner_by_id)
+    assert np.array_equal(ref.full_state(), got.full_state())
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_adaptive_bins_all_split_is_the_finer_uniform_grid(levels):
+    """Threshold 0 splits every occupied bin to the last level: the step
+    equals the uniform-grid step on the grid 2^levels times finer (its inv_h
+    is the exact power-of-two multiple), bit for bit, periodic seams
+    included."""
+    import dataclasses
+    w = I.c5_blobs(n=20_000, steps=2)
+    w.adapt_levels, w.adapt_threshold = levels, 0
+    b = w.boxes[0]
+    fine = dataclasses.replace(b, ncell=tuple(int(c) << levels for c in b.ncell))
+    assert all(fine.inv_h[k] == b.inv_h[k] * 2 ** levels for k in range(3))
+    wf = I.c5_blobs(n=20_000, steps=2)
+    wf.boxes = [fine]
+    a, c = O.Run(w), O.Run(wf)
+    for _ in range(2):
+        assert a.step() == c.step()
+        assert np.array_equal(a.partner_by_id, c.partner_by_id)
+    assert np.array_equal(a.full_state(), c.full_state())
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_adaptive_bins_equal_pure_geometry_when_reach_fits_the_finest_bin(periodic):
+    """With reach sqrt(D^2 + (g_max dt)^2) below the finest sub-bin every
+    acceptable pair lies in touching leaves, whatever the levels: the
+    adaptive search equals the all-pairs search that knows nothing of
+    bins."""
+    rng = np.random.default_rng(77 if periodic else 78)
+    tot = 0
+    for trial in range(4):
+        n = int(rng.integers(900, 1400))
+        nc = 4
+        L = 2
+        hf = 1.0 / (nc << L)
+        D = 0.8 * hf
+        box, s = _clustered(rng, n, periodic, nc, D, 1.0, nclust=2, width=0.03)
+        vmax = float(np.sqrt((s[3:6] ** 2).sum(axis=0)).max())
+        box.dt = 0.999 * math.sqrt(hf * hf - D * D) / (2.0 * vmax)
+        ids = rng.permutation(n).astype(np.uint32)
+        pa, _ = O.find_partners(box, s, ids, nthreads=4, adapt=(L, 4))
+        pg, margin = _geometric_partners(s, D * D, box.dt, 1.0, periodic, ids)
+        assert margin > 1e-9
+        assert np.array_equal(pa, pg), f"trial {trial}"
+        tot += int((pa >= 0).sum())
+    assert tot > 50
+
+
+def test_adaptive_bins_worked_case():
+    """Two bins side by side along x (edge 1/4): the left holds one
+    particle, the right five, split once with threshold 2 into sub-bins of
+    edge 1/8.  A partner 0.2 D ahead of the left particle, in the right bin's
+    near sub-bin, is in its neighbourhood; the same partner moved into the
+    far sub-bin (still within D) is not, so the left particle has none; and
+    with the right bin whole (threshold 5) it is a partner again."""
+    D = 0.2
+    box = I.Box(n=6, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), ncell=(4, 4, 4), D2=D * D, dt=1.0)
+    s = np.zeros((6, 6))
+    s[0:3, 0] = (0.2, 0.3, 0.3)          # left bin (0, 1, 1)
+    s[3, 0] = 0.5
+    # right bin (1, 1, 1): four particles far in its corner sub-bin ...
+    s[0:3, 1:5] = np.array([[0.49, 0.49, 0.49, 0.48], [0.49, 0.48, 0.49, 0.49], [0.49, 0.49, 0.48, 0.49]])
+    s[3:6, 1:5] = np.array([[0.0, 0.0, 0.0, 0.0], [0.1, -0.1, 0.2, -0.2], [0.3, 0.3, -0.3, -0.3]])
+    # ... and the candidate, approaching head-on 0.2 D off axis
+    s[0:3, 5] = (0.2 + 0.06, 0.3 + 0.2 * D, 0.3)
+    s[3, 5] = -0.5
+    ids = np.arange(6, dtype=np.uint32)
+    near, _ = O.find_partners(box, s, ids, adapt=(1, 2))
+    assert near[0] == 5 and near[5] == 0
+    s[0, 5] = 0.2 + 0.18                 # x = 0.38: sub-bin [3/8, 1/2) of the right bin
+    far, _ = O.find_partners(box, s, ids, adapt=(1, 2))
+    assert far[0] == -1
+    whole, _ = O.find_partners(box, s, ids, adapt=(1, 5))
+    assert whole[0] == 5
+    for thr in (2, 5):
+        bf, _ = O.find_partners(box, s, ids, brute=True, adapt=(1, thr))
+        assert np.array_equal(bf, O.find_partners(box, s, ids, adapt=(1, thr))[0])
