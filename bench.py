@@ -4,20 +4,25 @@ Workload (the headline configuration): N = 1e8 particles uniform in a ball
 of radius 1 with radial infall v = -0.5 x + N(0, 0.1^2), reflecting sphere,
 399^3 cells of edge ~D (about three particles per cell), seeded synthetic
 input.  The plain FP64 path and the FP32-screen path each run W untimed and K
-timed steps from the same initial state; their per-step pair counts and
-digests must be identical.  `value` is the FP32-screen path's particle-steps/s
-when that path is built, else the FP64 path's.
+timed steps from the same initial state, replayed from a captured hipGraph as
+a caller would run them; `value` is the FP32-screen path's particle-steps/s
+when that path is built, else the FP64 path's.  Their per-step pair counts
+and digests must be identical to each other and, for the headline workload,
+to the oracle's record of the same run (tests/golden/full_c3_sphere.json).
 
-Per-phase times come from HIP events the library records on the launch
-stream around every phase (profile mode).  The roofline object describes the
-dominant kernel (the partner search).  `cpu_baseline` times the CPU oracle
-(test infrastructure) on a bounded sample of the same workload.
+A second run of each path from the same initial state records HIP events on
+the launch stream around every phase (profile mode, no graph): the per-phase
+times and the search kernel's average launch time, from which the roofline
+object of the dominant kernel (the partner search) is computed.
+`cpu_baseline` times the CPU oracle (test infrastructure) on a bounded sample
+of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
                     [--workload c3_sphere|c2_shock|c4_batch|c5_blobs|c6_mixture] [--dt-rule adaptive]
+                    [--search half|full] [--autotune none|launch|cells] [--ppc-sweep]
 
-The other workloads (shock tube, 256-box batch, Gaussian blobs) print the same
-line for their own configuration; the headline is c3_sphere.
+The other workloads (shock tube, 256-box batch, Gaussian blobs, mixture)
+print the same line for their own configuration; the headline is c3_sphere.
 """
 import argparse
 import hashlib
@@ -31,17 +36,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s at N=1e8 (FP32-screen vs plain FP64, identical pair lists)"
-# Algorithmic floating-point operations of one pair evaluation (an FMA counts
-# 2): r, g: 6 subtractions; b, g2: 2 x (1 mul + 2 fma) = 10; c = r x g:
-# 3 x (1 mul + 1 fma) = 9; c2: 1 mul + 2 fma = 5; dt*g2, D2*g2: 2.  The pair
-# quantities are symmetric, so one evaluation decides both orders of an
-# unordered neighbour pair: the search kernel evaluates pair_tests / 2.
-FLOP_PER_PAIR_EVAL = 32
-PEAK_VALU_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP64, or unpacked FP32)
+# Algorithmic floating-point operations of one ordered pair test (an FMA
+# counts 2): r, g: 6 subtractions; b, g2: 2 x (1 mul + 2 fma) = 10;
+# c = r x g: 3 x (1 mul + 1 fma) = 9; c2: 1 mul + 2 fma = 5; the thresholds
+# dt*g2 and D2*g2: 2; the comparisons g2 > 0, b <= 0, -b <= dt g2,
+# c2 < D2 g2 and the argmin: 5 -> 37.  A pair test is one ordered (i, j != i)
+# pair of i's 27-cell neighbourhood, counted alike for both paths.
+FLOP_PER_PAIR_TEST = 37
+# Published vector peaks of MI355X: FP32 157.3 TFLOP/s (packed FP32), FP64
+# and unpacked FP32 78.6 TFLOP/s (256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz).
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# Algorithmic HBM bytes per particle-step of the FP64 step (bin 32, scan ~5,
-# sorted copy 116, search 52, resolve/scatter/stream 110).
+# Algorithmic HBM bytes per particle-step of the whole FP64 step (bin 32,
+# scan ~5, sorted copy 116, search 52, resolve/scatter/stream 110).
 STEP_BYTES_PER_PARTICLE = 315
+# Algorithmic HBM bytes per particle of one search launch: read the sorted
+# records once (FP64 48 B, FP32 screen 24 B) and write the result (4 B).
+SEARCH_BYTES_PER_PARTICLE = {"fp64": 52, "fp32_screen": 28}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_{}.json")
 
 
 def log(*a):
@@ -70,33 +83,61 @@ def traffic_for(path_name, launches_bytes):
     return None if e is None else e.get("bytes_per_launch")
 
 
-def run_path(kmc, w, precision, steps, warmup, pair_tests, search_mode=0):
+def _sim(kmc, w, precision, search_mode, block_size, steps, warmup, tile=0, **mode):
+    kinds = None if w.species is None else (w.species, w.radius, w.mass)
+    return kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=precision,
+                   history=max(64, steps + warmup), dt_rule=w.dt_rule,
+                   dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search_mode,
+                   block_size=block_size, kinds=kinds, tile=tile, adapt_levels=w.adapt_levels,
+                   adapt_threshold=w.adapt_threshold, **mode)
+
+
+def run_path(kmc, w, precision, steps, warmup, search_mode=0, block_size=0, tile=0):
+    """One path timed twice from the same initial state: (1) graph replay,
+    the step as a caller runs it (value, ms/step, the per-step history);
+    (2) profile mode, HIP events on the launch stream around every phase and
+    around the search kernel alone, plus the pair tests of every step."""
     import torch
     name = "fp64" if precision == kmc.KMC_FP64 else "fp32_screen"
-    log(f"[bench] {name}: init N={w.n}")
-    kinds = None if w.species is None else (w.species, w.radius, w.mass)
-    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=precision,
-                  history=max(64, steps + warmup), profile=True, dt_rule=w.dt_rule,
-                  dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search_mode, kinds=kinds)
+    log(f"[bench] {name}: init N={w.n} (graph replay)")
+    sim = _sim(kmc, w, precision, search_mode, block_size, steps, warmup, tile, use_graph=True)
     sim.step(warmup)
     torch.cuda.synchronize()
     s0 = sim.stats()
-    if pair_tests is None:
-        pair_tests = sim.pair_tests()
     log(f"[bench] {name}: warmup done, timing {steps} steps")
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     s1 = sim.stats()
     hn, hd = sim.history()
-    ms_phase = {k: (s1["ms"][k] - s0["ms"][k]) / steps for k in s1["ms"]}
-    search_kernel_ms = (s1["search_kernel_ms"] - s0["search_kernel_ms"]) / steps
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    log(f"[bench] {name}: {1e3 * el / steps:.3f} ms/step (graph); profiling the phases")
+
+    sim = _sim(kmc, w, precision, search_mode, block_size, steps, warmup, tile, profile=True)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    p0 = sim.stats()
+    tests = []
+    for _ in range(steps):
+        sim.step(1)
+        tests.append(sim.pair_tests())   # a separate kernel between steps: outside every phase
+    torch.cuda.synchronize()
+    p1 = sim.stats()
+    ph = sim.history()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    ms_phase = {k: (p1["ms"][k] - p0["ms"][k]) / steps for k in p1["ms"]}
+    search_kernel_ms = (p1["search_kernel_ms"] - p0["search_kernel_ms"]) / steps
     out = dict(
         value=w.n * steps / el,
         ms_per_step=1e3 * el / steps,
+        timing="hipGraph replay",
         ms_phase=ms_phase,
+        ms_per_step_profiled=sum(ms_phase.values()),
         search_kernel_ms=search_kernel_ms,
         rechecks_per_step=(s1["rechecks"] - s0["rechecks"]) / steps,
         fallbacks=s1["fallbacks"] - s0["fallbacks"],
@@ -104,16 +145,44 @@ def run_path(kmc, w, precision, steps, warmup, pair_tests, search_mode=0):
         # FP32 screen the pairs it could not reject (decided again in FP64)
         candidates_per_particle_step=(s1["candidates"] - s0["candidates"]) / (steps * w.n),
         history=[(int(a), int(b)) for a, b in zip(hn, hd)],
-        pair_tests=pair_tests,
+        profiled_history_equal=[(int(a), int(b)) for a, b in zip(*ph)] == [(int(a), int(b)) for a, b in zip(hn, hd)],
+        pair_tests=sum(tests) / len(tests),
     )
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    log(f"[bench] {name}: {out['ms_per_step']:.3f} ms/step, search kernel {search_kernel_ms:.3f} ms")
+    log(f"[bench] {name}: search kernel {search_kernel_ms:.3f} ms, profiled step {out['ms_per_step_profiled']:.3f} ms")
     return out
 
 
-def workload(name, n, dt_rule):
+def golden_check(name, n, results):
+    """Compare each path's per-step (pair count, digest) with the oracle's
+    record of the same run, where one exists for this workload and size."""
+    f = GOLDEN.format(name)
+    if not os.path.exists(f):
+        return None
+    with open(f) as fh:
+        g = json.load(fh)
+    if g["input"]["n"] != n:
+        return None
+    want = [(int(e["npairs"]), int(e["digest"], 16)) for e in g["per_step"]]
+    out = {"file": os.path.relpath(f, ROOT)}
+    for k, r in results.items():
+        m = min(len(want), len(r["history"]))
+        out[k] = r["history"][:m] == want[:m]
+        out["steps_compared"] = m
+    return out
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def workload(name, n, dt_rule, adapt=None):
     from paper_1310_3437_amd import inputs
     if name == "c3_sphere":
         w = inputs.c3_sphere(n=n)
@@ -147,6 +216,10 @@ def workload(name, n, dt_rule):
         w.boxes = [dataclasses.replace(b, dt=10.0 * b.dt) for b in w.boxes]
         w.dt_rule = 1
         desc += "; adaptive dt = dx / v_max (cap 10x the fixed dt)"
+    if adapt:
+        w.adapt_levels, w.adapt_threshold = adapt
+        desc += (f"; density-adaptive bins: a cell is split (up to {adapt[0]} halvings) while it holds more "
+                 f"than {adapt[1]} x 8^level particles")
     return w, desc
 
 
@@ -163,21 +236,29 @@ def cpu_workload(name, n_sample):
     return inputs.c5_blobs(n=n_sample, steps=1), f"the c5_blobs recipe at N={n_sample:.0e} (same particles per cell)"
 
 
-def cpu_baseline(name, n_sample):
+def cpu_baseline(name, n_sample, steps):
     from oracle import oracle as O
     w, what = cpu_workload(name, n_sample)
-    log(f"[bench] cpu baseline: oracle step on {what}")
+    log(f"[bench] cpu baseline: {steps} oracle steps on {what}")
     r = O.Run(w)
-    n_sample = w.n
     nt = O.lib().orc_max_threads()
+    tests = 0
     t0 = time.perf_counter()
-    r.step()
+    for _ in range(steps):
+        r.step()
+        tests += r.pair_tests
     el = time.perf_counter() - t0
-    return dict(value=n_sample / el, unit="particle-steps/s", cores=int(nt), kind="oracle",
-                sample=f"one oracle step (search with {nt} OpenMP threads, serial bin/resolve/stream) "
-                       f"of {what}, {el:.1f} s; {r.pair_tests / el:.3e} pair-tests/s",
-                pair_tests_per_s=r.pair_tests / el, seconds=el,
-                cpu=platform.processor() or platform.machine())
+    out = dict(value=w.n * steps / el, unit="particle-steps/s", cores=int(nt), kind="oracle",
+               sample=f"{steps} oracle steps (search with {nt} OpenMP threads, serial bin/resolve/stream) "
+                      f"of {what}, {el:.1f} s; {tests / el:.3e} pair-tests/s",
+               pair_tests_per_s=tests / el, seconds=el, cpu=cpu_model(), nproc=os.cpu_count())
+    g = GOLDEN.format(name)
+    if os.path.exists(g):
+        with open(g) as fh:
+            ctx = json.load(fh)["oracle_context"]
+        # the whole-run record written with the oracle (its own machine)
+        out["full_run_record"] = dict(ctx, file=os.path.relpath(g, ROOT))
+    return out
 
 
 def ppc_sweep(kmc, args):
@@ -229,10 +310,19 @@ def main():
     ap.add_argument("--workload", default="c3_sphere")
     ap.add_argument("--n", type=float, default=None, help="particles (default: the workload's full size)")
     ap.add_argument("--dt-rule", default="fixed", choices=("fixed", "adaptive"))
-    ap.add_argument("--search", default="half", choices=("half", "full"),
-                    help="partner-search organisation (the result is the same)")
+    ap.add_argument("--search", default=None, choices=("half", "full"),
+                    help="partner-search organisation (the result is the same; default half, or the "
+                         "autotuner's choice)")
+    ap.add_argument("--autotune", default=None, choices=("none", "launch", "cells"),
+                    help="kmc_autotune before timing: launch (search organisation, block size; results "
+                         "unchanged) or cells (also the cell edge, which changes the partner criteria); "
+                         "default cells for c4_batch, launch for c5_blobs, none otherwise")
+    ap.add_argument("--adapt", default=None,
+                    help="density-adaptive bins L,T (at most L halvings of a cell, split while it holds more than "
+                         "T 8^level particles); changes the neighbourhoods, so it is a variant of the workload")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=None)
+    ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--paths", default="fp64,fp32")
     ap.add_argument("--ppc-sweep", action="store_true",
                     help="wall time against particles per cell (Fig. 1 study) instead of the benchmark")
@@ -245,7 +335,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1310_3437_amd import inputs, kmc
+    from paper_1310_3437_amd import kmc
     kmc.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
@@ -258,35 +348,62 @@ def main():
         raise SystemExit(f"bench.py: unknown workload {args.workload}")
     n_arg = args.n if args.n is not None else full[args.workload]
     t0 = time.perf_counter()
-    w, desc = workload(args.workload, int(n_arg) if n_arg else None, args.dt_rule)
+    adapt = tuple(int(x) for x in args.adapt.split(",")) if args.adapt else None
+    if adapt:
+        args.search = "full"
+    w, desc = workload(args.workload, int(n_arg) if n_arg else None, args.dt_rule, adapt)
     n = w.n
     log(f"[bench] generated {args.workload} N={n} in {time.perf_counter() - t0:.1f} s")
 
-    results = {}
-    pair_tests = None
-    have_f32 = "fp32" in args.paths and os.environ.get("KMC_BENCH_NO_F32") is None
-    for name in args.paths.split(","):
+    tune = args.autotune or dict(c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
+    paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32")]
+    if os.environ.get("KMC_BENCH_NO_F32") is not None:
+        paths = [p for p in paths if p != "fp32"]
+    results, tuned = {}, {}
+    for name in paths:
         prec = kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
-        if name == "fp32" and not have_f32:
-            continue
-        r = run_path(kmc, w, prec, args.steps, args.warmup, pair_tests,
-                     kmc.KMC_SEARCH_FULL if args.search == "full" else kmc.KMC_SEARCH_HALF)
-        pair_tests = r["pair_tests"]
-        results[name] = r
+        search = kmc.KMC_SEARCH_FULL if args.search == "full" else kmc.KMC_SEARCH_HALF
+        block, tile = 0, 0
+        wp = w
+        if tune != "none":
+            flags = kmc.KMC_TUNE_LAUNCH | (kmc.KMC_TUNE_CELLS if tune == "cells" else 0)
+            kinds = None if w.species is None else (w.species, w.radius, w.mass)
+            log(f"[bench] {name}: autotune ({tune})")
+            nb, cfg, info = kmc.autotune(w.boxes, w.state, device="cuda:0", flags=flags, steps=3, kinds=kinds,
+                                         precision=prec, seed=w.seed, dt_rule=w.dt_rule,
+                                         dt_factor=w.dt_factor if w.dt_rule else 0.0, search_mode=search,
+                                         adapt_levels=w.adapt_levels, adapt_threshold=w.adapt_threshold)
+            import dataclasses
+            wp = dataclasses.replace(w, boxes=nb)
+            search, block, tile = cfg["search_mode"], cfg["block_size"], cfg["tile"]
+            best = info["tried"][info["best"]]
+            tuned[name] = dict(search_mode="full" if search == kmc.KMC_SEARCH_FULL else "half",
+                               block_size=block, tile=tile, kappa=best["kappa"],
+                               ms_per_step_tuning=best["ms_per_step"], candidates=len(info["tried"]))
+        results[name] = run_path(kmc, wp, prec, args.steps, args.warmup, search, block, tile)
+        results[name]["search"] = "full" if search == kmc.KMC_SEARCH_FULL else "half"
 
+    same_grid = len({json.dumps(t.get("kappa")) for t in tuned.values()}) <= 1
     identical = None
-    if "fp64" in results and "fp32" in results:
+    if "fp64" in results and "fp32" in results and same_grid:
         identical = results["fp64"]["history"] == results["fp32"]["history"]
-    head = results.get("fp32") or results["fp64"]
-    head_name = "fp32_screen" if "fp32" in results else "fp64"
+    golden = golden_check(args.workload, n, results) if (args.dt_rule == "fixed" and tune != "cells"
+                                                          and not adapt) else None
+    if golden is not None and identical is not None:
+        identical = identical and all(golden[k] for k in results)
+    head_key = "fp32" if "fp32" in results else "fp64"
+    head = results[head_key]
+    head_name = "fp32_screen" if head_key == "fp32" else "fp64"
     search_ms = head["search_kernel_ms"]
-    # the half-neighbourhood search evaluates each unordered pair once, the
-    # full one each ordered pair
-    evals = head["pair_tests"] // 2 if args.search == "half" else head["pair_tests"]
-    flops = FLOP_PER_PAIR_EVAL * evals
-    achieved = flops / (search_ms * 1e-3) / 1e12
+    tests = head["pair_tests"]
+    achieved = FLOP_PER_PAIR_TEST * tests / (search_ms * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if head_name == "fp32_screen" else PEAK_FP64_TFLOPS
+    # the half-neighbourhood search evaluates each unordered pair once
+    evals = tests / 2 if head["search"] == "half" else tests
+    executed = FLOP_PER_PAIR_TEST * evals / (search_ms * 1e-3) / 1e12
+    sbytes = SEARCH_BYTES_PER_PARTICLE[head_name] * n
     headline = (args.workload == "c3_sphere" and n == 100_000_000 and args.dt_rule == "fixed"
-                and args.search == "half")
+                and head["search"] == "half")
     traffic = traffic_for(head_name, None) if headline else None
     metric = METRIC if args.workload == "c3_sphere" and n == 100_000_000 else \
         f"particle-steps/s on {args.workload} (FP32-screen vs plain FP64, identical pair lists)"
@@ -307,20 +424,33 @@ def main():
             "workload": desc,
             "N": n,
             "path": head_name,
+            "search": head["search"],
+            "timing": "hipGraph replay",
         },
         "roofline": {
-            "kernel": f"k_search_{args.search}<" + ("PolF32" if head_name == "fp32_screen" else "PolF64")
+            "kernel": ("k_search_full + k_search_adapt<" if adapt else f"k_search_{head['search']}<")
+                      + ("PolF32" if head_name == "fp32_screen" else "PolF64")
                       + ("<true>>" if w.species is not None else "<false>>")
                       + (" (FP32 screen)" if head_name == "fp32_screen" else " (FP64)"),
             "bound": "alu",
             "achieved": achieved,
-            "peak": PEAK_VALU_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_VALU_TFLOPS,
+            "frac": achieved / peak,
             "traffic": traffic,
-            "flop_per_pair_eval": FLOP_PER_PAIR_EVAL,
-            "pair_evals_per_launch": evals,
+            "flop_per_pair_test": FLOP_PER_PAIR_TEST,
+            "pair_tests_per_launch": tests,
             "avg_launch_ms": search_ms,
+            # the same flops per evaluation the kernel executes (each unordered
+            # pair once in the half search), against the FP64 / unpacked-FP32
+            # rate that code without packed FP32 can reach
+            "executed": {"pair_evals_per_launch": evals, "achieved": executed, "peak": PEAK_FP64_TFLOPS,
+                         "frac": executed / PEAK_FP64_TFLOPS},
+            # algorithmic bytes of the search (read the sorted records once,
+            # write the result) per launch time, against HBM peak
+            "hbm_algorithmic": {"bytes_per_particle": SEARCH_BYTES_PER_PARTICLE[head_name],
+                                "achieved_GBs": sbytes / (search_ms * 1e-3) / 1e9,
+                                "frac": sbytes / (search_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
         },
         "roofline_step": {
             "bound": "hbm",
@@ -330,10 +460,13 @@ def main():
             "frac": STEP_BYTES_PER_PARTICLE * n / (head["ms_per_step"] * 1e-3) / 1e9 / PEAK_HBM_GBS,
             "bytes_per_particle_step": STEP_BYTES_PER_PARTICLE,
         },
-        "pair_tests_per_s": head["pair_tests"] * head["value"] / n,
+        "pair_tests_per_s": tests * head["value"] / n,
         "identical_pair_lists": identical,
+        "oracle_record_match": golden,
         "paths": {k: {kk: vv for kk, vv in v.items() if kk != "history"} for k, v in results.items()},
     }
+    if tuned:
+        line["autotuned"] = tuned
     if "fp64" in results and "fp32" in results:
         line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
     if args.copy_calibration:
@@ -347,7 +480,7 @@ def main():
         del src, dst
     if not args.no_cpu:
         cs = args.cpu_sample if args.cpu_sample is not None else sample[args.workload]
-        line["cpu_baseline"] = cpu_baseline(args.workload, int(cs) if cs else None)
+        line["cpu_baseline"] = cpu_baseline(args.workload, int(cs) if cs else None, args.cpu_steps)
     print(json.dumps(line), flush=True)
 
 

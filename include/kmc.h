@@ -182,7 +182,11 @@ typedef struct kmc_config {
                                   with 0 < s = e1*e1 + e2*e2 < 1 of the same random
                                   numbers, n = ((e1*e1 - e2*e2) / s,
                                   ((2*e1)*e2) / s, 0)                                    */
-    int32_t reserved[2];       /* must be zero                                           */
+    int32_t tile;              /* tile shape of the partner-search kernel: 0 (default), 1
+                                  (small LDS chunks) or 2 (large chunks, fewer waves per
+                                  SIMD); the results do not depend on it (a launch
+                                  choice, see kmc_autotune)                              */
+    int32_t reserved;          /* must be zero                                           */
     double guard_scale;        /* FP32 screen: factor applied to the derived rounding-error
                                   bounds; 0 = 4 (default), >= 1 otherwise.  -1 disables the
                                   bounds (testing only: the screen is then not exact)     */
@@ -192,7 +196,27 @@ typedef struct kmc_config {
                                    masses); otherwise the kinds described above (host
                                    pointer, read by kmc_workspace_bytes, kmc_init and
                                    kmc_autotune)                                        */
+    int32_t adapt_levels;      /* density-adaptive bins (below): 0 = the uniform grid;
+                                  1..3 = at most that many halvings of a bin            */
+    uint32_t adapt_threshold;  /* adaptive bins: a bin is split while it holds more than
+                                  adapt_threshold * 8^level particles (>= 1)             */
 } kmc_config;
+
+/* Density-adaptive bins (Section 1 proposes an adaptive bin size against the
+ * load imbalance of dense bins; Section 4: areas of higher density get
+ * smaller bins).  With adapt_levels = L > 0, at the start of every step each
+ * bin (cell) c of a box's grid holding n_c particles is split into
+ * 2^l x 2^l x 2^l equal sub-bins, l the smallest level in 0..L with
+ * n_c <= adapt_threshold * 8^l (L if none).  A particle's bin (its leaf) is
+ * the sub-bin it falls in: on the finest grid (ncell[k] * 2^L bins per axis,
+ * index clamp(floor((x - lo) * (inv_h * 2^L)), 0, ncell[k] * 2^L - 1)) a leaf
+ * spans an interval of indices on each axis.  Two particles are in each
+ * other's collision neighbourhood when their leaves touch: on every axis the
+ * intervals are at most one index apart (on a periodic axis with the image
+ * that makes them so).  An unsplit grid gives the 27-cell rule.  Requires
+ * search_mode KMC_SEARCH_FULL, dims 3, no absorbing faces and ncell[k] <=
+ * 2^27; the partners then differ from the uniform grid's wherever a bin is
+ * split. */
 
 /* Time step rules.
  *   KMC_DT_FIXED     every step of box b lasts boxes[b].dt.
@@ -331,9 +355,13 @@ int kmc_get_stats(kmc_ctx* ctx, kmc_stats* out, void* stream);
 
 /* Launch tuning.  kmc_autotune times short runs of candidate
  * configurations on the caller's input and returns the fastest.
- *   KMC_TUNE_LAUNCH  search organisation (kmc_search_mode) and threads per
+ *   KMC_TUNE_LAUNCH  search organisation (kmc_search_mode), tile shape of
+ *                    the search kernel (kmc_config.tile) and threads per
  *                    block of the streaming kernels; the results of the step
  *                    do not depend on these;
+ *   KMC_TUNE_PRECISION  also the precision of the pair test (KMC_FP64 or
+ *                    KMC_FP32_SCREEN): both give the same partners and states
+ *                    bit for bit, so this too is a speed choice only;
  *   KMC_TUNE_CELLS   also the cell edge: every box gets ncell[k] =
  *                    floor((hi[k] - lo[k]) / (kappa * sqrt(D2))) cells
  *                    (kappa in {1, 1.25, 1.5, 2}; at least 3 on periodic
@@ -343,9 +371,14 @@ int kmc_get_stats(kmc_ctx* ctx, kmc_stats* out, void* stream);
  *                    searched in the neighbouring bins), so this changes the
  *                    results: the caller must use the returned boxes
  *                    everywhere (including any reference it compares with). */
-enum { KMC_TUNE_LAUNCH = 1, KMC_TUNE_CELLS = 2 };
+enum { KMC_TUNE_LAUNCH = 1, KMC_TUNE_CELLS = 2, KMC_TUNE_PRECISION = 4 };
 
-#define KMC_TUNE_MAX 32
+/* The candidates are searched one coordinate at a time, for every cell grid
+ * (the given one, or each kappa with KMC_TUNE_CELLS): first the precisions
+ * (with KMC_TUNE_PRECISION) times the search organisations, then the other
+ * tile shapes, then the other block sizes (128, 512), each stage keeping the
+ * fastest so far.  At most KMC_TUNE_MAX candidates are timed. */
+#define KMC_TUNE_MAX 64
 typedef struct kmc_tuning {
     uint32_t ntried;                 /* candidates timed                           */
     uint32_t best;                   /* index of the chosen one                    */
@@ -353,18 +386,22 @@ typedef struct kmc_tuning {
     int32_t search_mode[KMC_TUNE_MAX];
     int32_t block_size[KMC_TUNE_MAX];
     double kappa[KMC_TUNE_MAX];      /* cell-edge factor (0: the given grid)       */
+    int32_t precision[KMC_TUNE_MAX];
+    int32_t tile[KMC_TUNE_MAX];
 } kmc_tuning;
 
 /* Time every candidate over `steps` steps (after one untimed step) from the
  * same input, choose the fastest, and write the chosen boxes and
  * configuration to out_boxes (nboxes entries; equal to `boxes` unless
- * KMC_TUNE_CELLS) and *out_cfg (cfg with search_mode and block_size set; the
- * other fields are copied).
+ * KMC_TUNE_CELLS) and *out_cfg (cfg with search_mode, tile, block_size and,
+ * with KMC_TUNE_PRECISION, precision set; the other fields are copied).
  *   d_state, d_workspace  as for kmc_init; the workspace must hold the
  *                    largest candidate (kmc_workspace_bytes of the boxes
- *                    with kappa = 1 and block_size 64 suffices); candidates
- *                    that do not fit are skipped;
- *   flags            KMC_TUNE_LAUNCH and/or KMC_TUNE_CELLS (0 = LAUNCH).
+ *                    with kappa = 1, block_size 64 and, with
+ *                    KMC_TUNE_PRECISION, precision KMC_FP32_SCREEN suffices);
+ *                    candidates that do not fit are skipped;
+ *   flags            KMC_TUNE_LAUNCH, KMC_TUNE_CELLS and/or KMC_TUNE_PRECISION
+ *                    (0 = LAUNCH).
  * d_state is only read.  Synchronises `stream`.  Errors as kmc_init, and
  * KMC_ENOMEM when no candidate fits. */
 int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,

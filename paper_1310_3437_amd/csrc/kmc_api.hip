@@ -17,7 +17,7 @@
 using namespace kmc;
 
 static_assert(sizeof(kmc_box) == 128, "kmc_box layout");
-static_assert(sizeof(kmc_config) == 88, "kmc_config layout");
+static_assert(sizeof(kmc_config) == 96, "kmc_config layout");
 static_assert(sizeof(kmc_species) == 144, "kmc_species layout");
 static_assert(KMC_MAX_SPECIES == kMaxKinds, "kind table stride");
 
@@ -87,8 +87,12 @@ int check_cfg(const kmc_config& c)
     if (c.search_mode != KMC_SEARCH_HALF && c.search_mode != KMC_SEARCH_FULL) return KMC_EINVAL;
     if (c.dims != 0 && c.dims != 2 && c.dims != 3) return KMC_EINVAL;
     if (c.dt_factor != 0.0 && !finite_pos(c.dt_factor)) return KMC_EINVAL;
-    for (int r : c.reserved)
-        if (r != 0) return KMC_EINVAL;
+    if (c.tile < 0 || c.tile > 2) return KMC_EINVAL;
+    if (c.reserved != 0) return KMC_EINVAL;
+    if (c.adapt_levels < 0 || c.adapt_levels > 3) return KMC_EINVAL;
+    if (c.adapt_levels > 0 &&
+        (c.adapt_threshold < 1 || c.search_mode != KMC_SEARCH_FULL || c.dims == 2))
+        return KMC_EINVAL;
     if (c.species) {
         const kmc_species& sp = *c.species;
         if (sp.count < 1 || sp.count > KMC_MAX_SPECIES || sp.reserved != 0) return KMC_EINVAL;
@@ -137,6 +141,10 @@ int validate(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, Total
     }
     int rc = check_cfg(*cfg);
     if (rc != KMC_OK) return rc;
+    if (cfg->adapt_levels > 0)
+        for (uint32_t b = 0; b < nboxes; ++b)
+            for (int k = 0; k < 3; ++k)
+                if (boxes[b].bc[k] == KMC_BC_ABSORB || boxes[b].ncell[k] > (1 << 27)) return KMC_EINVAL;
     if (cfg->dims == 2)
         for (uint32_t b = 0; b < nboxes; ++b)
             if (boxes[b].ncell[2] != 1 || boxes[b].bc[2] != KMC_BC_REFLECT || boxes[b].geometry != KMC_GEOM_BOX)
@@ -163,7 +171,9 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
         return ptr;
     };
     const size_t N = t.N, C = t.C;
-    const uint32_t H = history_len(cfg);
+    // one history row more than kept: each step clears the next row at its
+    // end, so the ring holds the last history_len steps plus that empty row
+    const uint32_t H = history_len(cfg) + 1u;
     const uint32_t nblk = (uint32_t)((C + kScanTile - 1) / kScanTile);
     const uint32_t cap = cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N;
     p.ctl = (Ctl*)take(sizeof(Ctl));
@@ -195,6 +205,25 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.recheck = (uint32_t*)take(4 * (size_t)(cap ? cap : 1));
     p.ovf = (uint2*)take(sizeof(uint2) * 2 * (N ? N : 1));
     p.cand_acc = (unsigned long long*)take(sizeof(unsigned long long) * kHistLanes);
+    p.adapt_L = cfg.adapt_levels;
+    p.adapt_T = cfg.adapt_threshold;
+    if (cfg.adapt_levels > 0) {
+        // leaf tables: a split bin at level l holds more than T 8^(l-1)
+        // particles, so the 8^l + 1 entries of all split bins number at most
+        // 8 N / T + N + 1
+        const size_t cap = 8 * N / cfg.adapt_threshold + N + 1;
+        p.level = (uint8_t*)take(C ? C : 1);
+        p.mixed = (uint8_t*)take(C ? C : 1);
+        p.pool_base = (uint32_t*)take(4 * (C ? C : 1));
+        p.refined = (uint32_t*)take(4 * (C ? C : 1));
+        p.pool = (uint32_t*)take(4 * cap);
+        p.leaf_slot = (uint32_t*)take(4 * (N ? N : 1));
+        p.pool_cap = (uint32_t)std::min<size_t>(cap, 0xFFFFFFFFu);
+    } else {
+        p.level = p.mixed = nullptr;
+        p.pool_base = p.refined = p.pool = p.leaf_slot = nullptr;
+        p.pool_cap = 0;
+    }
     p.nspecies = cfg.species ? (int32_t)cfg.species->count : 0;
     if (cfg.species) {
         p.spA = (uint8_t*)take(N ? N : 1);
@@ -222,6 +251,7 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.guard = cfg.guard_scale > 0.0 ? (float)cfg.guard_scale : (cfg.guard_scale < 0.0 ? 0.0f : 4.0f);
     p.dt_rule = cfg.dt_rule;
     p.search_mode = cfg.search_mode;
+    p.tile = cfg.tile;
     p.dims = cfg.dims == 2 ? 2 : 3;
     p.dt_factor = cfg.dt_factor != 0.0 ? cfg.dt_factor : 1.0;
     return off;
@@ -507,7 +537,8 @@ int kmc_read_history(kmc_ctx* c, uint64_t* h_npairs, uint64_t* h_digest, uint32_
     if (e == hipSuccess) e = hipMemcpyAsync(dg.data(), p.hist_dig, dg.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return KMC_EDEVICE;
-    uint64_t avail = ctl.steps_done < p.H ? ctl.steps_done : p.H;
+    const uint64_t kept = p.H - 1u;   // the ring's row after the newest is the next step's (cleared)
+    uint64_t avail = ctl.steps_done < kept ? ctl.steps_done : kept;
     if (avail > capacity) avail = capacity;
     for (uint64_t k = 0; k < avail; ++k) {
         const uint64_t step = ctl.steps_done - avail + k;
@@ -615,17 +646,15 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     if (rc != KMC_OK) return rc;
     if (t.N > 0 && !d_state) return KMC_EINVAL;
     if (flags == 0) flags = KMC_TUNE_LAUNCH;
-    if (flags & ~(uint32_t)(KMC_TUNE_LAUNCH | KMC_TUNE_CELLS)) return KMC_EINVAL;
+    if (flags & ~(uint32_t)(KMC_TUNE_LAUNCH | KMC_TUNE_CELLS | KMC_TUNE_PRECISION)) return KMC_EINVAL;
     if (steps == 0) steps = 3;
     if (steps > 1000) return KMC_EINVAL;
 
     std::vector<double> kappas{0.0};
     if (flags & KMC_TUNE_CELLS) kappas = {1.0, 1.25, 1.5, 2.0};
-    std::vector<int32_t> modes{cfg->search_mode}, blocks{cfg->block_size ? cfg->block_size : 256};
-    if (flags & KMC_TUNE_LAUNCH) {
-        modes = {KMC_SEARCH_HALF, KMC_SEARCH_FULL};
-        blocks = {128, 256, 512};
-    }
+    std::vector<int32_t> precs{cfg->precision};
+    if (flags & KMC_TUNE_PRECISION) precs = {KMC_FP64, KMC_FP32_SCREEN};
+    const bool launch = (flags & KMC_TUNE_LAUNCH) != 0;
     std::memset(out, 0, sizeof(*out));
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -638,43 +667,84 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     double best_ms = INFINITY;
     int status = KMC_OK;
     uint32_t k = 0;
+    // time one candidate (NaN when it cannot run: grid or workspace); returns
+    // its ms per step
+    auto trial = [&](const kmc_config& c, double kappa, bool grid_ok) -> double {
+        if (k >= KMC_TUNE_MAX || status != KMC_OK) return NAN;
+        out->search_mode[k] = c.search_mode;
+        out->block_size[k] = c.block_size;
+        out->kappa[k] = kappa;
+        out->precision[k] = c.precision;
+        out->tile[k] = c.tile;
+        out->ms_per_step[k] = NAN;
+        size_t need = 0;
+        kmc_ctx* ctx = nullptr;
+        double r = NAN;
+        if (grid_ok && kmc_workspace_bytes(bx.data(), nboxes, &c, &need) == KMC_OK && need <= workspace_bytes &&
+            kmc_init(bx.data(), nboxes, &c, d_state, d_workspace, workspace_bytes, stream, &ctx) == KMC_OK) {
+            float ms = 0.f;
+            hipError_t e = kmc_step(ctx, 1, stream) == KMC_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
+            if (e == hipSuccess) e = kmc_step(ctx, steps, stream) == KMC_OK ? hipEventRecord(e1, s) : hipErrorUnknown;
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            kmc_destroy(ctx);
+            if (e != hipSuccess) {
+                status = KMC_EDEVICE;
+            } else {
+                r = (double)ms / steps;
+                out->ms_per_step[k] = r;
+                if (r < best_ms) {
+                    best_ms = r;
+                    out->best = k;
+                    best_boxes = bx;
+                    best_cfg = c;
+                }
+            }
+        }
+        ++k;
+        return r;
+    };
     for (double kappa : kappas) {
         bool ok = true;
         for (uint32_t b = 0; b < nboxes && ok; ++b)
             ok = kappa == 0.0 ? (bx[b] = boxes[b], true) : kmc_box_with_kappa(&boxes[b], kappa, &bx[b]) == KMC_OK;
-        for (int32_t mode : modes)
-            for (int32_t blk : blocks) {
-                if (k >= KMC_TUNE_MAX) break;
-                out->search_mode[k] = mode;
-                out->block_size[k] = blk;
-                out->kappa[k] = kappa;
-                out->ms_per_step[k] = NAN;
-                kmc_config c = *cfg;
+        kmc_config base = *cfg;
+        base.use_graph = 0;
+        base.profile = 0;
+        if (launch) {
+            base.block_size = 256;
+            base.tile = 0;
+        }
+        // stage 1: precision x search organisation
+        kmc_config cur = base;
+        double cur_ms = INFINITY;
+        const std::vector<int32_t> modes = launch ? std::vector<int32_t>{KMC_SEARCH_HALF, KMC_SEARCH_FULL}
+                                                  : std::vector<int32_t>{cfg->search_mode};
+        for (int32_t pr : precs)
+            for (int32_t mode : modes) {
+                kmc_config c = base;
+                c.precision = pr;
                 c.search_mode = mode;
-                c.block_size = blk;
-                c.use_graph = 0;
-                c.profile = 0;
-                size_t need = 0;
-                kmc_ctx* ctx = nullptr;
-                if (ok && kmc_workspace_bytes(bx.data(), nboxes, &c, &need) == KMC_OK && need <= workspace_bytes &&
-                    kmc_init(bx.data(), nboxes, &c, d_state, d_workspace, workspace_bytes, stream, &ctx) == KMC_OK) {
-                    float ms = 0.f;
-                    hipError_t e = kmc_step(ctx, 1, stream) == KMC_OK ? hipEventRecord(e0, s) : hipErrorUnknown;
-                    if (e == hipSuccess) e = kmc_step(ctx, steps, stream) == KMC_OK ? hipEventRecord(e1, s) : hipErrorUnknown;
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    kmc_destroy(ctx);
-                    if (e != hipSuccess) { status = KMC_EDEVICE; break; }
-                    out->ms_per_step[k] = ms / steps;
-                    if (ms / steps < best_ms) {
-                        best_ms = ms / steps;
-                        out->best = k;
-                        best_boxes = bx;
-                        best_cfg = c;
-                    }
-                }
-                ++k;
+                const double r = trial(c, kappa, ok);
+                if (r < cur_ms) { cur_ms = r; cur = c; }
             }
+        if (launch && std::isfinite(cur_ms)) {
+            // stage 2: the other tile shapes; stage 3: the other block sizes
+            const kmc_config t0 = cur;
+            for (int32_t tile : {1, 2}) {
+                kmc_config c = t0;
+                c.tile = tile;
+                const double r = trial(c, kappa, ok);
+                if (r < cur_ms) { cur_ms = r; cur = c; }
+            }
+            const kmc_config b0 = cur;
+            for (int32_t blk : {128, 512}) {
+                kmc_config c = b0;
+                c.block_size = blk;
+                const double r = trial(c, kappa, ok);
+                if (r < cur_ms) { cur_ms = r; cur = c; }
+            }
+        }
         if (status != KMC_OK) break;
     }
     out->ntried = k;
@@ -686,6 +756,8 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     *out_cfg = *cfg;
     out_cfg->search_mode = best_cfg.search_mode;
     out_cfg->block_size = best_cfg.block_size;
+    out_cfg->tile = best_cfg.tile;
+    out_cfg->precision = best_cfg.precision;
     return KMC_OK;
 }
 

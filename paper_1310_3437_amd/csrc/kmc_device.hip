@@ -25,6 +25,41 @@ __device__ __forceinline__ int cell1(double x, double lo, double inv_h, int n)
     return (int)f;
 }
 
+// Density-adaptive bins: index of a point on the finest grid (n 2^L cells)
+// along one axis, clamp(floor((x - lo) * (inv_h * 2^L)), 0, n 2^L - 1).
+// inv_h * 2^L is exact and the power-of-two scaling commutes with the
+// rounding of the product, so the point's cell is this index >> L.
+__device__ __forceinline__ int fine1(double x, double lo, double inv_h, int n, int L)
+{
+    const double f = floor((x - lo) * (inv_h * (double)(1 << L)));
+    if (!(f >= 0.0)) return 0;
+    const double m = (double)n * (double)(1 << L);
+    if (f >= m) return (int)(m - 1.0);
+    return (int)f;
+}
+
+// Split level of a cell holding `count` particles: the smallest l in 0..L
+// with count <= T 8^l, else L.
+__device__ __forceinline__ uint32_t split_level(uint32_t count, uint32_t T, int L)
+{
+    for (int l = 0; l < L; ++l)
+        if ((uint64_t)count <= ((uint64_t)T << (3 * l))) return (uint32_t)l;
+    return (uint32_t)L;
+}
+
+// Index of the sub-bin (leaf) a point falls in inside its cell split at
+// level lvl: the sub-bin coordinates are bits L-lvl .. L-1 of the finest
+// indices, linearised x fastest.
+__device__ __forceinline__ uint32_t leaf_code(const BoxDev& B, int L, uint32_t lvl, double x, double y, double z)
+{
+    const int sh = L - (int)lvl;
+    const uint32_t m = (1u << lvl) - 1u;
+    const uint32_t sx = ((uint32_t)fine1(x, B.lo[0], B.inv_h[0], B.nc[0], L) >> sh) & m;
+    const uint32_t sy = ((uint32_t)fine1(y, B.lo[1], B.inv_h[1], B.nc[1], L) >> sh) & m;
+    const uint32_t sz = ((uint32_t)fine1(z, B.lo[2], B.inv_h[2], B.nc[2], L) >> sh) & m;
+    return sx + (m + 1u) * (sy + (m + 1u) * sz);
+}
+
 // Image of a partner along one axis, from the two cell indices: the
 // partner's image is shifted by -L (+L) when it sits in the last (first)
 // cell of a periodic axis and the other particle in the first (last).
@@ -408,6 +443,8 @@ __global__ __launch_bounds__(1024) void k_scan_partials(Plan p)
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
         p.ctl->ovf_count = 0;
+        p.ctl->refined_count = 0;
+        p.ctl->pool_used = 0;
     }
     for (uint32_t b = threadIdx.x; b < p.nboxes; b += blockDim.x) p.box_vmax[b] = 0u;
 }
@@ -448,6 +485,123 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) p.start[p.C] = p.N;
+    if (p.adapt_L > 0) {
+        // adaptive bins: this step's split level of every cell from its count;
+        // split cells are listed and claim their leaf tables
+        uint64_t lv = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const uint32_t c = base + k;
+            if (c < p.C) {
+                const uint32_t l = split_level(v[k], p.adapt_T, p.adapt_L);
+                lv |= (uint64_t)l << (8 * k);
+                if (l) {
+                    p.refined[atomicAdd(&p.ctl->refined_count, 1u)] = c;
+                    p.pool_base[c] = atomicAdd(&p.ctl->pool_used, (1u << (3 * l)) + 1u);
+                }
+            }
+        }
+        if (base + kScanItems <= p.C) {
+            *reinterpret_cast<uint64_t*>(p.level + base) = lv;
+            *reinterpret_cast<uint64_t*>(p.mixed + base) = 0ull;
+        } else {
+            for (int k = 0; k < kScanItems; ++k)
+                if (base + k < p.C) {
+                    p.level[base + k] = (uint8_t)(lv >> (8 * k));
+                    p.mixed[base + k] = 0;
+                }
+        }
+    }
+}
+
+// Box of a global cell (the boxes' cells are consecutive, in box order).
+__device__ __forceinline__ uint32_t box_of_cell(const Plan& p, uint32_t c)
+{
+    uint32_t lo = 0, hi = p.nboxes - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (p.boxes[mid].coff <= c) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Adaptive bins, per split cell (one wave each): clear its leaf counts and
+// mark it and its 26 neighbours as cells whose particles' neighbourhoods
+// are not the plain 27 cells.
+__global__ __launch_bounds__(64) void k_refined_prep(Plan p)
+{
+    const uint32_t n = p.ctl->refined_count;
+    const uint32_t lane = threadIdx.x;
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const uint32_t c = p.refined[k];
+        const uint32_t m = 1u << (3u * p.level[c]);
+        const uint32_t pb = p.pool_base[c];
+        for (uint32_t t = lane; t < m; t += 64u) p.pool[pb + t] = 0u;
+        if (lane < 27u) {
+            const BoxDev& B = p.boxes[box_of_cell(p, c)];
+            const uint32_t loc = c - B.coff, NX = (uint32_t)B.nc[0], NY = (uint32_t)B.nc[1];
+            int q[3] = {(int)(loc % NX), (int)((loc / NX) % NY), (int)(loc / (NX * NY))};
+            const int d[3] = {(int)(lane % 3u) - 1, (int)((lane / 3u) % 3u) - 1, (int)(lane / 9u) - 1};
+            bool ok = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                q[a] += d[a];
+                if (q[a] < 0) { if (B.periodic[a]) q[a] += B.nc[a]; else ok = false; }
+                else if (q[a] >= B.nc[a]) { if (B.periodic[a]) q[a] -= B.nc[a]; else ok = false; }
+            }
+            if (ok) p.mixed[B.coff + (uint32_t)q[0] + NX * ((uint32_t)q[1] + NY * (uint32_t)q[2])] = 1;
+        }
+    }
+}
+
+// Adaptive bins: each particle of a split cell counts itself into its leaf;
+// the returned value is its rank in the leaf.
+__global__ void k_leaf_count(Plan p)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.N) return;
+    const uint32_t c = p.cell[i];
+    const uint32_t lvl = p.level[c];
+    if (lvl == 0u) return;
+    const size_t N = p.N;
+    const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, p.A[i], p.A[N + i], p.A[2 * N + i]);
+    p.leaf_slot[i] = atomicAdd(&p.pool[p.pool_base[c] + code], 1u);
+}
+
+// Adaptive bins, per split cell (one wave each): the exclusive prefix of its
+// leaf counts in place (leaf starts relative to the cell's start), then the
+// cell's count after the last.
+__global__ __launch_bounds__(64) void k_leaf_scan(Plan p)
+{
+    const uint32_t n = p.ctl->refined_count;
+    const int lane = threadIdx.x;
+    for (uint32_t k = blockIdx.x; k < n; k += gridDim.x) {
+        const uint32_t c = p.refined[k];
+        const uint32_t m = 1u << (3u * p.level[c]);
+        uint32_t* t = p.pool + p.pool_base[c];
+        const uint32_t per = m > 64u ? m / 64u : 1u;    // entries per lane (m is 8, 64 or 512)
+        const uint32_t b0 = (uint32_t)lane * per;
+        uint32_t v[8];
+        uint32_t sum = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < 8u; ++e) {
+            v[e] = (e < per && b0 + e < m) ? t[b0 + e] : 0u;
+            sum += v[e];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        uint32_t run = x - sum;
+#pragma unroll
+        for (uint32_t e = 0; e < 8u; ++e) {
+            if (e < per && b0 + e < m) t[b0 + e] = run;
+            run += v[e];
+        }
+        if (lane == 63) t[m] = x;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -466,11 +620,20 @@ __global__ void k_scatter(Plan p)
     bool outside = false;
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (valid) {
-        const uint32_t d = p.start[p.cell[i]] + p.slot[i];
         P64 r;
         r.x = p.A[i];
         r.y = p.A[N + i];
         r.z = p.A[2 * N + i];
+        const uint32_t c = p.cell[i];
+        uint32_t d;
+        const uint32_t lvl = p.adapt_L > 0 ? p.level[c] : 0u;
+        if (lvl) {
+            // adaptive bins: leaf-sorted inside a split cell
+            const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, r.x, r.y, r.z);
+            d = p.start[c] + p.pool[p.pool_base[c] + code] + p.leaf_slot[i];
+        } else {
+            d = p.start[c] + p.slot[i];
+        }
         r.vx = vx = p.A[3 * N + i];
         r.vy = vy = p.A[4 * N + i];
         r.vz = vz = p.A[5 * N + i];
@@ -481,6 +644,7 @@ __global__ void k_scatter(Plan p)
         if (id & kGone) vx = vy = vz = 0.0;   // not in the gas: no part in the adaptive step
         if (F32) {
             vm = fmaxf(fabsf((float)r.vx), fmaxf(fabsf((float)r.vy), fabsf((float)r.vz)));
+
             // The screen's error bounds take every particle to lie inside the
             // cell it is binned in (up to a slack of 1e-9 of a cell edge).  A
             // particle outside its box's grid (placed there, or moved more
@@ -711,6 +875,7 @@ __device__ __forceinline__ uint32_t wcode(int wx, int wy, int wz)
 {
     return (uint32_t)(wx + 1) | ((uint32_t)(wy + 1) << 2) | ((uint32_t)(wz + 1) << 4);
 }
+constexpr uint32_t kNoImage = 0x15u;   // wcode(0, 0, 0)
 
 struct Found {
     uint32_t* sj; // this lane's kept indices in LDS: pair k at sj[64 k] (one store per pair
@@ -840,16 +1005,38 @@ struct Best {
     }
 };
 
+// Tile shape of a search kernel: W records staged per LDS chunk, and the
+// waves per SIMD the half- and full-neighbourhood searches are compiled for
+// (fewer waves leave more registers per wave).  The launch autotuner picks
+// one of three shapes per precision (kmc_config.tile); the results do not
+// depend on it.
+template <int W_, int HALF_WAVES, int FULL_WAVES>
+struct Tile {
+    static constexpr int W = W_;
+    static constexpr int kWaves = HALF_WAVES;
+    static constexpr int kFullWaves = FULL_WAVES;
+};
+// FP64: 96 records per chunk (4.5 KiB) by default
+using TileF64_0 = Tile<96, 6, 5>;
+using TileF64_1 = Tile<64, 6, 5>;
+using TileF64_2 = Tile<160, 5, 4>;
+// FP32 screen: 128 records (4 KiB) by default (measured against 96, 160,
+// 192 and 256 on the headline gas)
+using TileF32_0 = Tile<128, 6, 5>;
+using TileF32_1 = Tile<64, 6, 5>;
+using TileF32_2 = Tile<256, 5, 4>;
+
 // K: particles of several kinds (the pair's D2 from the per-kind-pair table,
 // staged in LDS with each record's kind); otherwise the box's D2.
-template <bool K>
+template <bool K, class T = TileF64_0>
 struct PolF64 {
-    static constexpr int W = 96;          // staged records per chunk (4.5 KiB)
+    static constexpr int W = T::W;
     static constexpr bool kScreen = false;
     static constexpr bool kKinds = K;
     static constexpr int kFlushBatch = 2;
     static constexpr bool kFlushSkipEmpty = true;
-    static constexpr int kWaves = 6;      // waves per SIMD the half search is compiled for
+    static constexpr int kWaves = T::kWaves;
+    static constexpr int kFullWaves = T::kFullWaves;
     struct Lds {
         P64 rec[W];
         uint8_t kind[K ? W : 1];
@@ -875,7 +1062,7 @@ struct PolF64 {
     }
     __device__ static P64 self64(const Plan&, uint32_t, const Own& o) { return o.me; }
     __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev&, const Group&,
-                                 int, int, int)
+                                 int, int, int, int, int)
     {
         l.rec[t] = p.B[j];
         if (K) l.kind[t] = p.spB[j];
@@ -912,6 +1099,31 @@ struct PolF64 {
             const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
             const double d2 = K ? l.d2[o.row + l.kind[j - c0]] : D2;
             if (accept(pq, d2, dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
+        }
+    }
+    // adaptive bins: the staged candidates t = u, u + kk, ... (< n) against
+    // owner io; candidate t is sorted particle lj[t] seen with the periodic
+    // image of code lw[t]
+    __device__ static void scan_adapt(const Plan&, const Lds& l, const uint32_t* lid, const uint32_t* lj,
+                                      const uint32_t* lw, uint32_t n, uint32_t u, uint32_t kk, uint32_t io,
+                                      const Own& o, const BoxDev& B, const Group&, Best& best)
+    {
+        const double D2 = B.D2, dt = B.dt;
+        for (uint32_t t = u; t < n; t += kk) {
+            const uint32_t j = lj[t];
+            if (j == io) continue;
+            const P64 q = l.rec[t];
+            double rx = q.x - o.me.x, ry = q.y - o.me.y, rz = q.z - o.me.z;
+            const uint32_t w = lw[t];
+            if (w != kNoImage) {
+                const int wx = (int)(w & 3u) - 1, wy = (int)((w >> 2) & 3u) - 1, wz = (int)((w >> 4) & 3u) - 1;
+                if (wx != 0) rx = rx + (double)wx * B.L[0];
+                if (wy != 0) ry = ry + (double)wy * B.L[1];
+                if (wz != 0) rz = rz + (double)wz * B.L[2];
+            }
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - o.me.vx, q.vy - o.me.vy, q.vz - o.me.vz);
+            const double d2 = K ? l.d2[o.row + l.kind[t]] : D2;
+            if (accept(pq, d2, dt)) best.offer(pq.c2 / pq.g2, lid[t], j);
         }
     }
 };
@@ -1106,15 +1318,15 @@ __global__ void k_screen_bounds(Plan p)
 
 // K: particles of several kinds (the screen's folded D2 constant of each
 // pair of kinds from a per-box table in LDS); otherwise the box's constant.
-template <bool K>
+template <bool K, class T = TileF32_0>
 struct PolF32 {
-    static constexpr int W = 128;         // staged records per chunk (4 KiB; measured
-                                          // against 96, 160, 192 and 256)
+    static constexpr int W = T::W;
     static constexpr bool kScreen = true;
     static constexpr bool kKinds = K;
     static constexpr int kFlushBatch = 2;
     static constexpr bool kFlushSkipEmpty = true;
-    static constexpr int kWaves = 6;
+    static constexpr int kWaves = T::kWaves;
+    static constexpr int kFullWaves = T::kFullWaves;
     // A staged candidate is two 16-byte halves in two arrays: a = x, y, z
     // relative to the group centre and vx; b = vy, vz, its kind (particle
     // kinds only) and its sorted index (bit patterns).  With 16-byte strides
@@ -1174,7 +1386,7 @@ struct PolF32 {
     // velocity, each rounded once.  Rows without an image (almost all) skip
     // the shift (the row's shift is the same for the whole wave).
     __device__ static void stage(Lds& l, uint32_t t, const Plan& p, uint32_t j, const BoxDev& B, const Group& g,
-                                 int wx, int wy, int wz)
+                                 int wx, int wy, int wz, int, int)
     {
         const P64 q = p.B[j];
         double x = q.x, y = q.y, z = q.z;
@@ -1247,11 +1459,44 @@ struct PolF32 {
             }
         }
     }
+    // adaptive bins: as PolF64::scan_adapt, every pair the screen keeps
+    // decided in FP64 with the candidate's image
+    __device__ static void scan_adapt(const Plan& p, const Lds& l, const uint32_t* lid, const uint32_t*,
+                                      const uint32_t* lw, uint32_t n, uint32_t u, uint32_t kk, uint32_t io,
+                                      const Own& o, const BoxDev& B, const Group& g, Best& best)
+    {
+        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
+        for (uint32_t t = u; t < n; t += kk) {
+            const float4 qa = l.a[t];
+            const float4 qb = l.b[t];
+            const uint32_t j = __float_as_uint(qb.w);
+            const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
+            const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
+            const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
+            const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+            const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
+            const uint32_t kj = K ? __float_as_uint(qb.z) : 0u;
+            const float kd = K ? l.kd2[o.row + kj] : kD2;
+            const float mb = fmaf(-tb1, g2, b);
+            const float m2 = fmaf(-kdt, g2, -b);
+            const float m3 = fmaf(rr - kd, g2, -(b * b));
+            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != io)) {
+                const P64 me = p.B[io], q = p.B[j];
+                double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
+                const uint32_t w = lw[t];
+                if (w != kNoImage) {
+                    const int wx = (int)(w & 3u) - 1, wy = (int)((w >> 2) & 3u) - 1, wz = (int)((w >> 4) & 3u) - 1;
+                    if (wx != 0) rx6 = rx6 + (double)wx * B.L[0];
+                    if (wy != 0) ry6 = ry6 + (double)wy * B.L[1];
+                    if (wz != 0) rz6 = rz6 + (double)wz * B.L[2];
+                }
+                const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+                best.screened += 1u;
+                if (accept(pq, K ? p.sp_D2[o.row + kj] : B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[t], j);
+            }
+        }
+    }
 };
-
-// Waves per SIMD the full-neighbourhood search is compiled for (its FP32
-// variant spills at six).
-constexpr int kFullWaves = 5;
 
 template <class Pol>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kWaves)))
@@ -1311,7 +1556,8 @@ void k_search_half(Plan p)
             const bool sh = (wx | wy | wz) != 0;
             for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
                 const uint32_t n = min((uint32_t)Pol::W, ge - c0);
-                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u)
+                    Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz, dy, dz);
                 __syncthreads();
                 const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
                 if (sh) Pol::template scan<true>(p, lds, c0, j0, j1, i, own, B, gctx, wx, wy, wz, dy, dz, found);
@@ -1379,7 +1625,7 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
     const int lane = threadIdx.x;
     const uint32_t i = tile * 64u + (uint32_t)lane;
     const bool valid = i < p.N;
-    const bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
+    bool alive = valid && !(p.idB[i] & kGone);   // absorbed particles do not search
     uint32_t bidx = 0, rowkey = 0xFFFFFFFFu;
     int cx = 0, cy = 0, cz = 0;
     typename Pol::Own own{};
@@ -1392,6 +1638,9 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
         cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
         cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
         rowkey = B.coff + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+        // adaptive bins: particles in or next to a split cell search their
+        // touching leaves instead (k_search_adapt)
+        if (p.adapt_L > 0 && p.mixed[rowkey + (uint32_t)cx]) alive = false;
     }
     Best best;
     best.key = __builtin_inf();
@@ -1428,7 +1677,7 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
             for (uint32_t c0 = gs; c0 < ge; c0 += (uint32_t)Pol::W) {
                 const uint32_t n = min((uint32_t)Pol::W, ge - c0);
                 for (uint32_t t = (uint32_t)lane; t < n; t += 64u) {
-                    Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz);
+                    Pol::stage(lds, t, p, c0 + t, B, gctx, wx, wy, wz, dy, dz);
                     lid[t] = p.idB[c0 + t];
                 }
                 __syncthreads();
@@ -1464,7 +1713,7 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
             }
         }
     }
-    if (valid) p.partner[i] = best.j;
+    if (valid && (alive || p.adapt_L == 0)) p.partner[i] = best.j;
     if (STATS) {
         // statistics: pairs accepted (FP64) or decided in FP64 (FP32 screen)
         uint64_t c = Pol::kScreen ? best.screened : best.accepted;
@@ -1475,7 +1724,7 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
 }
 
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
 void k_search_full(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -1489,9 +1738,11 @@ void k_search_full(Plan p)
 // screen's safe range.  A fixed grid of waves that exits at once unless the
 // step's flag is set, and otherwise takes the tiles in turn.
 constexpr uint32_t kFallbackBlocks = 4096;
+// Waves that walk the list of split cells (adaptive bins).
+constexpr uint32_t kAdaptPrepBlocks = 4096;
 
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kFullWaves)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
 void k_fallback_full(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -1499,6 +1750,276 @@ void k_fallback_full(Plan p)
     if (p.ctl->overflow == 0u) return;
     const uint32_t ntiles = (p.N + 63u) / 64u;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) search_full_tile<Pol, false>(p, t, lds, lid);
+}
+
+// --------------------------------------------------------------------------
+// Density-adaptive bins: the search of particles in or next to a split cell.
+//
+// Particles of one leaf share their neighbourhood: the leaves that touch
+// theirs, all inside the 27 cells around their cell.  A wave takes 64
+// consecutive sorted particles; the lanes of one leaf form a group (they are
+// consecutive, the sort keeps leaves contiguous).  For each group the wave
+// lists the sorted ranges of the touching leaves, stages their particles
+// into LDS and tests every (owner, candidate) pair with all 64 lanes: each of
+// the group's g owners gets 64 / g' lanes (g' the next power of two), which
+// take every (64/g')-th staged candidate, and the owner's (key, id) minimum
+// is reduced over its lanes.  Each pair is tested from both sides (running
+// minimum, no lists).
+// --------------------------------------------------------------------------
+
+// The leaves of the neighbour cell (c + d) that touch the leaf [lo, hi]
+// (finest indices per axis) of a particle in cell c, as ranges of the sorted
+// arrays: f(s, e, code) once per run of touching leaves that is contiguous
+// in the cell's leaf order (one range for an unsplit cell); code packs the
+// periodic image (wcode) and the cell offset d.  Nothing when the neighbour
+// cell does not exist or no leaf of it touches.
+template <class F>
+__device__ __forceinline__ void neighbour_leaves(const Plan& p, const BoxDev& B, const int c[3], const int lo[3],
+                                                 const int hi[3], int dx, int dy, int dz, F&& f)
+{
+    const int L = p.adapt_L;
+    const int d[3] = {dx, dy, dz};
+    int q[3], w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q[a] = c[a] + d[a];
+        w[a] = 0;
+        if (q[a] < 0) { if (!B.periodic[a]) return; q[a] += B.nc[a]; w[a] = -1; }
+        else if (q[a] >= B.nc[a]) { if (!B.periodic[a]) return; q[a] -= B.nc[a]; w[a] = 1; }
+    }
+    const uint32_t cell = B.coff + (uint32_t)q[0] + (uint32_t)B.nc[0] * ((uint32_t)q[1] + (uint32_t)B.nc[1] * (uint32_t)q[2]);
+    const int lvl = (int)p.level[cell];
+    const int sh = L - lvl, r = 1 << lvl;
+    int jlo[3], jhi[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // leaf j of the neighbour spans [b0 + j 2^sh, b0 + (j + 1) 2^sh - 1]
+        // (b0: its lower face, with the image); it touches [lo, hi] iff
+        // (lo - b0 - 1) >> sh <= j <= (hi + 1 - b0) >> sh
+        const long long b0 = ((long long)q[a] << L) + (long long)w[a] * ((long long)B.nc[a] << L);
+        jlo[a] = (int)max(0ll, ((long long)lo[a] - b0 - 1) >> sh);
+        jhi[a] = (int)min((long long)(r - 1), ((long long)hi[a] + 1 - b0) >> sh);
+        if (jlo[a] > jhi[a]) return;
+    }
+    const uint32_t code = wcode(w[0], w[1], w[2]) | ((uint32_t)wcode(dx, dy, dz) << 6);
+    const uint32_t s0 = p.start[cell];
+    if (lvl == 0) {
+        f(s0, p.start[cell + 1], code);
+        return;
+    }
+    const uint32_t* t = p.pool + p.pool_base[cell];
+    for (int jz = jlo[2]; jz <= jhi[2]; ++jz)
+        for (int jy = jlo[1]; jy <= jhi[1]; ++jy) {
+            const uint32_t row = (uint32_t)r * ((uint32_t)jy + (uint32_t)r * (uint32_t)jz);
+            f(s0 + t[row + (uint32_t)jlo[0]], s0 + t[row + (uint32_t)jhi[0] + 1u], code);
+        }
+}
+
+// A particle's cell (c) and leaf ([lo, hi] in finest indices) under adaptive
+// bins, from its position; returns the linear cell.
+__device__ __forceinline__ uint32_t leaf_of(const Plan& p, const BoxDev& B, double x, double y, double z, int c[3],
+                                            int lo[3], int hi[3], uint32_t& code)
+{
+    const int L = p.adapt_L;
+    const double xs[3] = {x, y, z};
+    int g[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g[a] = fine1(xs[a], B.lo[a], B.inv_h[a], B.nc[a], L);
+        c[a] = g[a] >> L;
+    }
+    const uint32_t cell = B.coff + (uint32_t)c[0] + (uint32_t)B.nc[0] * ((uint32_t)c[1] + (uint32_t)B.nc[1] * (uint32_t)c[2]);
+    const int lvl = (int)p.level[cell];
+    const int sh = L - lvl;
+    const uint32_t m = (1u << lvl) - 1u;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = (g[a] >> sh) << sh;
+        hi[a] = lo[a] + (1 << sh) - 1;
+    }
+    code = (((uint32_t)g[0] >> sh) & m) + (m + 1u) * ((((uint32_t)g[1] >> sh) & m) + (m + 1u) * (((uint32_t)g[2] >> sh) & m));
+    return cell;
+}
+
+constexpr int kRangeBatch = 128;
+
+template <int W>
+struct AdaptLds {
+    uint32_t rs[kRangeBatch];        // range starts (sorted index)
+    uint32_t rc[kRangeBatch];        // range codes (image, cell offset)
+    uint32_t rp[kRangeBatch + 1];    // exclusive prefix of the range sizes
+    uint32_t lid[W];                 // staged candidates' ids
+    uint32_t lj[W];                  // ... sorted indices
+    uint32_t lw[W];                  // ... image codes
+};
+
+// Binary search: the range r of flat candidate index f (rp[r] <= f < rp[r+1]).
+__device__ __forceinline__ uint32_t range_of(const uint32_t* rp, uint32_t nr, uint32_t f)
+{
+    uint32_t lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= f) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class Pol, bool STATS>
+__device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, typename Pol::Lds& lds,
+                                                  AdaptLds<Pol::W>& al)
+{
+    const int lane = threadIdx.x;
+    const uint32_t i = tile * 64u + (uint32_t)lane;
+    bool alive = i < p.N && !(p.idB[i] & kGone);
+    uint32_t bidx = 0, cell = 0xFFFFFFFFu, code = 0;
+    int c[3] = {0, 0, 0}, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    if (alive) {
+        bidx = p.boxidx ? p.boxidx[i] : 0u;
+        const P64 me = p.B[i];
+        cell = leaf_of(p, p.boxes[bidx], me.x, me.y, me.z, c, lo, hi, code);
+        alive = p.mixed[cell] != 0;
+    }
+    Best best;
+    uint64_t nstat = 0;
+    uint64_t remaining = __ballot(alive);
+    while (remaining) {
+        const int lead = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t gcell = (uint32_t)__builtin_amdgcn_readlane((int)cell, lead);
+        const uint32_t gcode = (uint32_t)__builtin_amdgcn_readlane((int)code, lead);
+        const uint64_t grp = __ballot(alive && cell == gcell && code == gcode) & remaining;
+        remaining &= ~grp;
+        const uint32_t g = (uint32_t)__popcll(grp);   // lanes lead .. lead + g - 1 (a leaf is contiguous)
+        const uint32_t gb = (uint32_t)__builtin_amdgcn_readlane((int)bidx, lead);
+        const BoxDev& B = p.boxes[gb];
+        int gc[3], glo[3], ghi[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            gc[a] = __builtin_amdgcn_readlane(c[a], lead);
+            glo[a] = __builtin_amdgcn_readlane(lo[a], lead);
+            ghi[a] = __builtin_amdgcn_readlane(hi[a], lead);
+        }
+        // owners: 64 / g' lanes each (g' = g rounded up to a power of two)
+        uint32_t gp = 1;
+        while (gp < g) gp <<= 1;
+        const uint32_t kk = 64u / gp, o = (uint32_t)lane / kk, u = (uint32_t)lane % kk;
+        const bool owner = o < g;
+        const uint32_t io = tile * 64u + (uint32_t)lead + (owner ? o : 0u);
+        typename Pol::Own own{};
+        double ox, oy, oz;
+        Pol::load_own(p, io, own, ox, oy, oz);
+        typename Pol::Group gctx;
+        const uint32_t sbi = gb * (uint32_t)kSpanClasses;   // the neighbourhood spans 3 cells: class 0
+        Pol::begin_group(p, B, own, gctx, gc[0], gc[0], gc[1], gc[2], (int)sbi, io, owner);
+        Pol::group_lds(lds, p, sbi, lane);
+        best.key = __builtin_inf();
+        best.id = 0xFFFFFFFFu;
+        best.j = -1;
+        best.accepted = 0u;
+        best.screened = 0u;
+        // ranges of the touching leaves: lanes 0..26 take one neighbour cell each
+        uint32_t nr = 0;
+        if (lane < 27)
+            neighbour_leaves(p, B, gc, glo, ghi, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1,
+                             [&](uint32_t, uint32_t, uint32_t) { ++nr; });
+        uint32_t off = nr;
+#pragma unroll
+        for (int sft = 1; sft < 64; sft <<= 1) {
+            const uint32_t y = __shfl_up(off, sft, 64);
+            if (lane >= sft) off += y;
+        }
+        const uint32_t R = (uint32_t)__shfl((int)off, 63, 64);
+        off -= nr;
+        for (uint32_t rb = 0; rb < R; rb += (uint32_t)kRangeBatch) {
+            const uint32_t nb = min((uint32_t)kRangeBatch, R - rb);
+            if (lane < 27 && nr) {
+                uint32_t k = off;
+                neighbour_leaves(p, B, gc, glo, ghi, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1,
+                                 [&](uint32_t s, uint32_t e, uint32_t cd) {
+                                     if (k >= rb && k < rb + nb) {
+                                         al.rs[k - rb] = s;
+                                         al.rc[k - rb] = cd;
+                                         al.rp[k - rb] = e - s;   // size, turned into the prefix below
+                                     }
+                                     ++k;
+                                 });
+            }
+            __syncthreads();
+            // exclusive prefix of the nb sizes: two per lane
+            const uint32_t e0 = 2u * (uint32_t)lane, e1 = e0 + 1u;
+            const uint32_t v0 = e0 < nb ? al.rp[e0] : 0u, v1 = e1 < nb ? al.rp[e1] : 0u;
+            uint32_t x = v0 + v1;
+#pragma unroll
+            for (int sft = 1; sft < 64; sft <<= 1) {
+                const uint32_t y = __shfl_up(x, sft, 64);
+                if (lane >= sft) x += y;
+            }
+            __syncthreads();
+            if (e0 < nb) al.rp[e0] = x - v0 - v1;
+            if (e1 < nb) al.rp[e1] = x - v1;
+            if (lane == 63) al.rp[nb] = x;
+            __syncthreads();
+            const uint32_t total = al.rp[nb];
+            for (uint32_t c0 = 0; c0 < total; c0 += (uint32_t)Pol::W) {
+                const uint32_t n = min((uint32_t)Pol::W, total - c0);
+                for (uint32_t t = (uint32_t)lane; t < n; t += 64u) {
+                    const uint32_t f = c0 + t;
+                    const uint32_t r = range_of(al.rp, nb, f);
+                    const uint32_t j = al.rs[r] + (f - al.rp[r]);
+                    const uint32_t cd = al.rc[r];
+                    const int wx = (int)(cd & 3u) - 1, wy = (int)((cd >> 2) & 3u) - 1, wz = (int)((cd >> 4) & 3u) - 1;
+                    const int dy = (int)((cd >> 8) & 3u) - 1, dz = (int)((cd >> 10) & 3u) - 1;
+                    Pol::stage(lds, t, p, j, B, gctx, wx, wy, wz, dy, dz);
+                    al.lid[t] = p.idB[j];
+                    al.lj[t] = j;
+                    al.lw[t] = cd & 0x3Fu;
+                }
+                __syncthreads();
+                if (owner) Pol::scan_adapt(p, lds, al.lid, al.lj, al.lw, n, u, kk, io, own, B, gctx, best);
+                __syncthreads();
+            }
+            __syncthreads();   // every read of this batch's ranges is done
+        }
+        // each owner's (key, id) minimum over its kk lanes
+        for (uint32_t sft = kk >> 1; sft > 0; sft >>= 1) {
+            const double k2 = __shfl_xor(best.key, (int)sft, 64);
+            const uint32_t id2 = (uint32_t)__shfl_xor((int)best.id, (int)sft, 64);
+            const int32_t j2 = __shfl_xor(best.j, (int)sft, 64);
+            if (k2 < best.key || (k2 == best.key && id2 < best.id)) {
+                best.key = k2;
+                best.id = id2;
+                best.j = j2;
+            }
+        }
+        if (owner && u == 0) p.partner[io] = best.j;
+        if (owner) nstat += Pol::kScreen ? best.screened : best.accepted;
+    }
+    if (STATS) {
+#pragma unroll
+        for (int sft = 32; sft > 0; sft >>= 1) nstat += __shfl_xor(nstat, sft, 64);
+        if (lane == 0 && nstat) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)nstat);
+    }
+}
+
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
+void k_search_adapt(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    __shared__ AdaptLds<Pol::W> al;
+    search_adapt_tile<Pol, true>(p, xcd_tile(blockIdx.x, gridDim.x), lds, al);
+}
+
+// The whole-step FP64 search of the particles k_search_adapt takes (see
+// k_fallback_full).
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
+void k_fallback_adapt(Plan p)
+{
+    __shared__ typename Pol::Lds lds;
+    __shared__ AdaptLds<Pol::W> al;
+    if (p.ctl->overflow == 0u) return;
+    const uint32_t ntiles = (p.N + 63u) / 64u;
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) search_adapt_tile<Pol, false>(p, t, lds, al);
 }
 
 // Pairs beyond a search lane's register slots: decided in FP64 and posted to
@@ -1835,7 +2356,18 @@ __global__ __launch_bounds__(256) void k_count_tests(Plan p, unsigned long long*
         const int cx = cell1(me.x, B.lo[0], B.inv_h[0], B.nc[0]);
         const int cy = cell1(me.y, B.lo[1], B.inv_h[1], B.nc[1]);
         const int cz = cell1(me.z, B.lo[2], B.inv_h[2], B.nc[2]);
-        for_each_range(B, cx, cy, cz, p.start, [&](uint32_t s, uint32_t e, int, int, int) { t += e - s; });
+        const uint32_t cell = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+        if (p.adapt_L > 0 && p.mixed[cell]) {
+            // adaptive bins: the particles of the touching leaves
+            int c[3], lo[3], hi[3];
+            uint32_t code;
+            leaf_of(p, B, me.x, me.y, me.z, c, lo, hi, code);
+            for (int k = 0; k < 27; ++k)
+                neighbour_leaves(p, B, c, lo, hi, k % 3 - 1, (k / 3) % 3 - 1, k / 9 - 1,
+                                 [&](uint32_t s, uint32_t e, uint32_t) { t += e - s; });
+        } else {
+            for_each_range(B, cx, cy, cz, p.start, [&](uint32_t s, uint32_t e, int, int, int) { t += e - s; });
+        }
         t -= 1;
     }
     block_sum2(t, z, lds);
@@ -1843,6 +2375,19 @@ __global__ __launch_bounds__(256) void k_count_tests(Plan p, unsigned long long*
 }
 
 inline uint32_t blocks_for(uint32_t n, uint32_t b) { return (n + b - 1) / b; }
+
+// The search kernel of one precision policy and tile shape.
+template <template <bool, class> class Pol, class T>
+void launch_search(bool kinds, bool full, uint32_t gW, hipStream_t s, const Plan& p)
+{
+    if (full) {
+        if (kinds) k_search_full<Pol<true, T>><<<gW, 64, 0, s>>>(p);
+        else k_search_full<Pol<false, T>><<<gW, 64, 0, s>>>(p);
+    } else {
+        if (kinds) k_search_half<Pol<true, T>><<<gW, 64, 0, s>>>(p);
+        else k_search_half<Pol<false, T>><<<gW, 64, 0, s>>>(p);
+    }
+}
 
 }  // namespace
 
@@ -1872,6 +2417,12 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     k_scan_reduce<<<p.nblk_scan, kScanBlock, 0, s>>>(p);
     k_scan_partials<<<1, 1024, 0, s>>>(p);
     k_scan_down<<<p.nblk_scan, kScanBlock, 0, s>>>(p);
+    if (p.adapt_L > 0 && p.N > 0) {
+        // adaptive bins: split cells' leaf tables, then every particle's rank in its leaf
+        k_refined_prep<<<kAdaptPrepBlocks, 64, 0, s>>>(p);
+        k_leaf_count<<<gN, b, 0, s>>>(p);
+        k_leaf_scan<<<kAdaptPrepBlocks, 64, 0, s>>>(p);
+    }
     mark(KMC_PHASE_SCATTER);
     if (p.N > 0) {
         if (p.precision == KMC_FP32_SCREEN) k_scatter<true><<<gN, b, 0, s>>>(p);
@@ -1887,23 +2438,24 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     if (ev) (void)hipEventRecord(ev[KMC_PHASE_COUNT + 1], s);   // search kernel alone
     const bool full = p.search_mode == KMC_SEARCH_FULL;
     if (p.N > 0) {
-        const bool f32 = p.precision == KMC_FP32_SCREEN, kinds = p.nspecies > 0;
-        if (full) {
-            if (f32) {
-                if (kinds) k_search_full<PolF32<true>><<<gW, 64, 0, s>>>(p);
-                else k_search_full<PolF32<false>><<<gW, 64, 0, s>>>(p);
-            } else {
-                if (kinds) k_search_full<PolF64<true>><<<gW, 64, 0, s>>>(p);
-                else k_search_full<PolF64<false>><<<gW, 64, 0, s>>>(p);
-            }
+        const bool kinds = p.nspecies > 0;
+        if (p.precision == KMC_FP32_SCREEN) {
+            if (p.tile == 1) launch_search<PolF32, TileF32_1>(kinds, full, gW, s, p);
+            else if (p.tile == 2) launch_search<PolF32, TileF32_2>(kinds, full, gW, s, p);
+            else launch_search<PolF32, TileF32_0>(kinds, full, gW, s, p);
         } else {
-            if (f32) {
-                if (kinds) k_search_half<PolF32<true>><<<gW, 64, 0, s>>>(p);
-                else k_search_half<PolF32<false>><<<gW, 64, 0, s>>>(p);
-            } else {
-                if (kinds) k_search_half<PolF64<true>><<<gW, 64, 0, s>>>(p);
-                else k_search_half<PolF64<false>><<<gW, 64, 0, s>>>(p);
-            }
+            if (p.tile == 1) launch_search<PolF64, TileF64_1>(kinds, full, gW, s, p);
+            else if (p.tile == 2) launch_search<PolF64, TileF64_2>(kinds, full, gW, s, p);
+            else launch_search<PolF64, TileF64_0>(kinds, full, gW, s, p);
+        }
+    }
+    if (p.N > 0 && p.adapt_L > 0) {
+        if (p.precision == KMC_FP32_SCREEN) {
+            if (p.nspecies > 0) k_search_adapt<PolF32<true>><<<gW, 64, 0, s>>>(p);
+            else k_search_adapt<PolF32<false>><<<gW, 64, 0, s>>>(p);
+        } else {
+            if (p.nspecies > 0) k_search_adapt<PolF64<true>><<<gW, 64, 0, s>>>(p);
+            else k_search_adapt<PolF64<false>><<<gW, 64, 0, s>>>(p);
         }
     }
     mark(KMC_PHASE_FINISH);
@@ -1917,6 +2469,10 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
     if (p.N > 0 && (!full || p.precision == KMC_FP32_SCREEN)) {
         if (p.nspecies > 0) k_fallback_full<PolF64<true>><<<kFallbackBlocks, 64, 0, s>>>(p);
         else k_fallback_full<PolF64<false>><<<kFallbackBlocks, 64, 0, s>>>(p);
+        if (p.adapt_L > 0) {
+            if (p.nspecies > 0) k_fallback_adapt<PolF64<true>><<<kFallbackBlocks, 64, 0, s>>>(p);
+            else k_fallback_adapt<PolF64<false>><<<kFallbackBlocks, 64, 0, s>>>(p);
+        }
     }
     mark(KMC_PHASE_RESOLVE);
     if (p.N > 0) {

@@ -77,7 +77,9 @@ struct Ctl {
     unsigned int recheck_count;         // this step's recheck list length
     unsigned int overflow;              // this step's flag for the whole-step FP64 search
     unsigned int ovf_count;             // this step's overflow pair list length
-    unsigned int pad_[3];
+    unsigned int refined_count;         // adaptive bins: bins split this step
+    unsigned int pool_used;             // adaptive bins: leaf-table entries claimed this step
+    unsigned int pad_;
 };
 
 // FP32 screen thresholds of one box for one step.  The bounds on the error
@@ -131,6 +133,19 @@ struct Plan {
     float guard;                   // FP32 screen: scale of the rounding-error bounds (>= 1)
     int32_t dt_rule;               // kmc_dt_rule
     int32_t search_mode;           // kmc_search_mode
+    int32_t tile;                  // tile shape of the search kernel (0, 1, 2)
+    // density-adaptive bins (adapt_L == 0: the uniform grid)
+    int32_t adapt_L;               // at most this many halvings of a bin
+    uint32_t adapt_T;              // split while more than adapt_T * 8^level particles
+    uint8_t* level;                // per cell: its split level this step
+    uint8_t* mixed;                // per cell: 1 if it or one of its 26 neighbours is split
+    uint32_t* pool_base;           // per split cell: first entry of its leaf table in pool
+    uint32_t* refined;             // the cells split this step (ctl->refined_count)
+    uint32_t* pool;                // leaf tables: per split cell 8^level counts, then their
+                                   // exclusive prefix (leaf starts relative to the cell's
+                                   // start) and the cell's count
+    uint32_t pool_cap;             // entries of pool
+    uint32_t* leaf_slot;           // per particle in A order: its rank in its leaf
     int32_t dims;                  // 3, or 2 for the planar mode
     double dt_factor;              // adaptive dt: C in dt = min(cap, C dx / v_max)
     // particle kinds (nspecies == 0: one kind, the box's D2, equal masses)

@@ -69,10 +69,13 @@ class KmcConfig(C.Structure):
         ("dt_rule", C.c_int32),
         ("search_mode", C.c_int32),
         ("dims", C.c_int32),
-        ("reserved", C.c_int32 * 2),
+        ("tile", C.c_int32),
+        ("reserved", C.c_int32),
         ("guard_scale", C.c_double),
         ("dt_factor", C.c_double),
         ("species", C.POINTER(KmcSpecies)),
+        ("adapt_levels", C.c_int32),
+        ("adapt_threshold", C.c_uint32),
     ]
 
 
@@ -98,8 +101,8 @@ EXPORTS = ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "
 KMC_SCRATCH_BYTES = 64 << 20
 
 
-KMC_TUNE_LAUNCH, KMC_TUNE_CELLS = 1, 2
-KMC_TUNE_MAX = 32
+KMC_TUNE_LAUNCH, KMC_TUNE_CELLS, KMC_TUNE_PRECISION = 1, 2, 4
+KMC_TUNE_MAX = 64
 
 
 class KmcTuning(C.Structure):
@@ -110,6 +113,8 @@ class KmcTuning(C.Structure):
         ("search_mode", C.c_int32 * KMC_TUNE_MAX),
         ("block_size", C.c_int32 * KMC_TUNE_MAX),
         ("kappa", C.c_double * KMC_TUNE_MAX),
+        ("precision", C.c_int32 * KMC_TUNE_MAX),
+        ("tile", C.c_int32 * KMC_TUNE_MAX),
     ]
 
 
@@ -203,7 +208,8 @@ def make_species(radius, mass, d_kind_ptr=0):
 
 def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR, history=0,
                 recheck_capacity=0, use_graph=False, block_size=0, profile=False, guard_scale=0.0,
-                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF, dims=3, species=None):
+                dt_rule=KMC_DT_FIXED, dt_factor=0.0, search_mode=KMC_SEARCH_HALF, dims=3, species=None, tile=0,
+                adapt_levels=0, adapt_threshold=0):
     """kmc_config from keyword arguments; species: a KmcSpecies (kept alive
     with the returned structure) or None for one kind of particle."""
     c = KmcConfig()
@@ -224,6 +230,9 @@ def make_config(seed=1, step0=0, precision=KMC_FP64, kinematics=KMC_KIN_AT_TSTAR
     c.dt_factor = float(dt_factor)
     c.search_mode = int(search_mode)
     c.dims = int(dims)
+    c.tile = int(tile)
+    c.adapt_levels = int(adapt_levels)
+    c.adapt_threshold = int(adapt_threshold)
     return c
 
 
@@ -253,6 +262,8 @@ def _tune_key(boxes, device_name, flags, steps, config, kinds=None):
                                                                           "use_graph", "species")},
                 boxes=[dict(n=int(b.n), lo=list(map(float, b.lo)), hi=list(map(float, b.hi)),
                             ncell=list(map(int, b.ncell)), periodic=list(map(bool, b.periodic)),
+                            absorb=list(map(bool, getattr(b, "absorb", (False,) * 3))),
+                            inv_h=[float(x).hex() for x in b.inv_h],
                             sphere=bool(b.sphere), R=float(b.R), D2=float(b.D2), dt=float(b.dt)) for b in boxes])
     return hashlib.sha256(json.dumps(desc, sort_keys=True).encode()).hexdigest()
 
@@ -276,7 +287,8 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
             if hit is not None:
                 kappa = hit["kappa"]
                 nb = [box_with_kappa(b, kappa) for b in boxes] if kappa > 0 else boxes
-                return nb, dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"]), \
+                return nb, dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"],
+                                tile=hit["tile"], precision=hit["precision"]), \
                     dict(best=hit["best"], tried=hit["tried"], cached=True)
     spc = {}
     if kinds is not None:
@@ -285,9 +297,13 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
     cfg = make_config(**config, **spc)
     arr = make_boxes(boxes)
     st = torch.as_tensor(state, dtype=torch.float64).to(device).contiguous()
-    # the largest candidate: the finest grid (kappa = 1) and the smallest blocks
+    # the largest candidate: the finest grid (kappa = 1), the smallest blocks
+    # and, when the precision is tuned, the FP32 screen's extra sorted copy
     probe = [box_with_kappa(b, 1.0) for b in boxes] if flags & KMC_TUNE_CELLS else boxes
-    need = workspace_bytes(probe, make_config(**dict(config, block_size=64), **spc))
+    pcfg = dict(config, block_size=64)
+    if flags & KMC_TUNE_PRECISION:
+        pcfg["precision"] = KMC_FP32_SCREEN
+    need = workspace_bytes(probe, make_config(**pcfg, **spc))
     ws = torch.empty(need + 256, dtype=torch.uint8, device=device)
     ptr = (ws.data_ptr() + 255) // 256 * 256
     out_b = (KmcBox * len(boxes))()
@@ -298,9 +314,10 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
                                C.c_size_t(need), int(flags), int(steps), stream, out_b, C.byref(out_c),
                                C.byref(tun)), "kmc_autotune")
     new_boxes = [_box_from_kmc(out_b[k], boxes[k]) for k in range(len(boxes))]
-    new_cfg = dict(config, search_mode=int(out_c.search_mode), block_size=int(out_c.block_size))
+    new_cfg = dict(config, search_mode=int(out_c.search_mode), block_size=int(out_c.block_size),
+                   tile=int(out_c.tile), precision=int(out_c.precision))
     tried = [dict(ms_per_step=tun.ms_per_step[k], search_mode=tun.search_mode[k], block_size=tun.block_size[k],
-                  kappa=tun.kappa[k]) for k in range(tun.ntried)]
+                  kappa=tun.kappa[k], precision=tun.precision[k], tile=tun.tile[k]) for k in range(tun.ntried)]
     if cache is not None:
         db = {}
         if os.path.exists(cache):
@@ -308,7 +325,7 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
                 db = json.load(fh)
         best = tried[int(tun.best)]
         db[key] = dict(search_mode=best["search_mode"], block_size=best["block_size"], kappa=best["kappa"],
-                       best=int(tun.best), tried=[{k: (None if isinstance(v, float) and v != v else v)
+                       tile=best["tile"], precision=best["precision"], best=int(tun.best), tried=[{k: (None if isinstance(v, float) and v != v else v)
                                                    for k, v in t.items()} for t in tried])
         tmp = cache + ".tmp"
         with open(tmp, "w") as fh:

@@ -46,10 +46,11 @@ def test_one_hip_runtime_whatever_the_import_order():
 
 
 def test_struct_sizes_match_header():
-    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes and the
-    # species pointer; kmc_species: two u32, 2 x 8 doubles, a pointer
+    # kmc_box: 32 bytes of ints, 12 doubles; kmc_config: 80 bytes, the
+    # species pointer and the two adaptive-bin words; kmc_species: two u32,
+    # 2 x 8 doubles, a pointer
     assert C.sizeof(kmc.KmcBox) == 128
-    assert C.sizeof(kmc.KmcConfig) == 88
+    assert C.sizeof(kmc.KmcConfig) == 96
     assert C.sizeof(kmc.KmcStats) == 136
     assert C.sizeof(kmc.KmcSpecies) == 144
 
@@ -120,7 +121,10 @@ def test_inv_h_must_match_the_grid(scale):
 @pytest.mark.parametrize("cfg", [
     dict(precision=7), dict(kinematics=3), dict(block_size=100), dict(block_size=2048),
     dict(dt_rule=2), dict(dt_rule=1, dt_factor=-1.0), dict(dt_rule=1, dt_factor=float("inf")),
-    dict(search_mode=2), dict(search_mode=-1), dict(dims=1), dict(dims=4),
+    dict(search_mode=2), dict(search_mode=-1), dict(dims=1), dict(dims=4), dict(tile=3), dict(tile=-1),
+    dict(adapt_levels=4, adapt_threshold=8, search_mode=1), dict(adapt_levels=-1),
+    dict(adapt_levels=2, adapt_threshold=0, search_mode=1),          # threshold must be >= 1
+    dict(adapt_levels=2, adapt_threshold=8, search_mode=0),          # needs the full search
 ])
 def test_invalid_configs_rejected(cfg):
     assert _ws([_good()], **cfg)[0] == kmc.KMC_EINVAL
@@ -129,7 +133,7 @@ def test_invalid_configs_rejected(cfg):
 def test_reserved_config_words_must_be_zero():
     arr = kmc.make_boxes([_good()])
     c = kmc.make_config()
-    c.reserved[1] = 1
+    c.reserved = 1
     n = C.c_size_t(0)
     assert kmc.load().kmc_workspace_bytes(arr, 1, C.byref(c), C.byref(n)) == kmc.KMC_EINVAL
 
@@ -226,3 +230,21 @@ def test_scratch_entry_point_rejects_oversized_boxes_before_any_device_work():
     assert L.kmc_init_scratch(kmc.make_boxes([bad]), 1, C.byref(cfg), None, None, C.byref(ctx)) == kmc.KMC_EINVAL
     assert L.kmc_init_scratch(kmc.make_boxes([_good()]), 1, C.byref(cfg), None, None, None) == kmc.KMC_EINVAL
     assert not ctx.value
+
+
+def test_adaptive_bins_validation():
+    """Adaptive bins need the full search, three dimensions, no absorbing
+    faces and at most 2^27 cells per axis."""
+    ok = dict(adapt_levels=3, adapt_threshold=8, search_mode=kmc.KMC_SEARCH_FULL)
+    assert _ws([_good()], **ok)[0] == 0
+    b = _good()
+    b.periodic = (False, True, True)
+    b.absorb = (True, False, False)
+    assert _ws([b], **ok)[0] == kmc.KMC_EINVAL
+    w = I.c1_planar()
+    assert _ws(w.boxes, dims=2, **ok)[0] == kmc.KMC_EINVAL
+    # the leaf tables: 8 N / T + N + 1 entries of 4 bytes, and per cell a
+    # level, a flag, a table offset and a list slot
+    n0 = _ws([_good()], search_mode=kmc.KMC_SEARCH_FULL)[1]
+    n1 = _ws([_good()], **ok)[1]
+    assert n1 >= n0 + 4 * (8 * 100 // 8 + 100 + 1) + 4 * 100 + 10 * 64

@@ -1,0 +1,97 @@
+"""GPU parity over whole runs of the benchmark workloads, at their full sizes
+and step counts, against the oracle's record of the same runs
+(tests/golden/full_<name>.json, written by tests/golden/make_full_runs.py
+with the CPU oracle alone).
+
+Every step: the partner array (the partner id of every particle id, -1 for
+none) must hash to the oracle's, and the step's collision count and digest
+must be the oracle's.  After the last step the (6, N) FP64 state in id order
+must hash to the oracle's (bit-exact; the sampled particles stored beside the
+hash give the size of any difference).  Both precisions run; the headline
+workload (c3_sphere at N = 1e8) runs in graph-replay mode, as the benchmark
+times it.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1310_3437_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _golden(name):
+    with open(os.path.join(HERE, "golden", f"full_{name}.json")) as f:
+        return json.load(f)
+
+
+def _sha(a):
+    h = hashlib.sha256()
+    mv = memoryview(np.ascontiguousarray(a)).cast("B")
+    for s in range(0, len(mv), 1 << 26):
+        h.update(mv[s:s + (1 << 26)])
+    return h.hexdigest()
+
+
+def _workload(g):
+    w = I.CONFIGS[g["workload"]](steps=g["steps"], **g["generator_kwargs"])
+    fp = g["input"]
+    assert w.n == fp["n"] and len(w.boxes) == fp["nboxes"]
+    assert [float(b.dt).hex() for b in w.boxes[:4]] == fp["dt"]
+    assert [float(b.D2).hex() for b in w.boxes[:4]] == fp["D2"]
+    assert _sha(w.state) == fp["state_sha256"], "the input generator no longer gives the recorded input"
+    return w
+
+
+def _check_run(kmc, w, g, precision, **cfg):
+    import torch
+    name = g["workload"]
+    prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+    print(f"\n[run] {name} N={w.n} steps={g['steps']} {precision} {cfg}", flush=True)
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=g["seed"], kinematics=g["kinematics"],
+                  precision=prec, history=max(64, g["steps"]), **cfg)
+    for e in g["per_step"]:
+        sim.step(1)
+        p = sim.partners().cpu().numpy()
+        assert p.dtype == np.int32
+        if _sha(p.astype("<i4")) != e["partners_sha256"]:
+            raise AssertionError(f"{name} {precision}: partner array differs from the oracle's at step {e['step']}")
+    hn, hd = sim.history()
+    got = [(int(a), int(b)) for a, b in zip(hn, hd)]
+    want = [(e["npairs"], int(e["digest"], 16)) for e in g["per_step"]]
+    assert got == want, f"{name} {precision}: per-step collision counts or digests differ"
+    st = sim.state()
+    ids = torch.as_tensor(np.asarray(g["sample_ids"], dtype=np.int64), device=st.device)
+    sample = st[:, ids].cpu().numpy()
+    ref = np.array([[float.fromhex(v) for v in row] for row in g["sample_state"]]).T
+    if _sha(st.cpu().numpy().astype("<f8")) != g["final_state_sha256"]:
+        scale = np.maximum(np.abs(ref).max(axis=1, keepdims=True), 1e-300)
+        rel = float((np.abs(sample - ref) / scale).max())
+        raise AssertionError(f"{name} {precision}: final state differs from the oracle's "
+                             f"(sampled max relative difference {rel:.3e})")
+    assert np.array_equal(sample, ref)
+    stats = sim.stats()
+    sim.close()
+    print(f"[run] ok: {sum(n for n, _ in got)} collisions over {len(got)} steps, "
+          f"rechecks {stats['rechecks']}, fallbacks {stats['fallbacks']}", flush=True)
+
+
+@pytest.mark.timeout(600)
+def test_c2_shock_1e6_200_steps(kmc):
+    g = _golden("c2_shock")
+    w = _workload(g)
+    _check_run(kmc, w, g, "fp32", use_graph=True)
+    _check_run(kmc, w, g, "fp64")
+
+
+@pytest.mark.timeout(600)
+def test_c4_batch_256_boxes_50_steps(kmc):
+    g = _golden("c4_batch")
+    w = _workload(g)
+    _check_run(kmc, w, g, "fp32", use_graph=True)
+    _check_run(kmc, w, g, "fp64", search_mode=kmc.KMC_SEARCH_FULL)

@@ -163,4 +163,13 @@ def test_autotune_with_kinds(kmc):
     assert np.isfinite(best["ms_per_step"])
     assert "species" not in cfg
     w.boxes = boxes
-    run_kinds(kmc, w, 2, "fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
+    run_kinds(kmc, w, 2, "fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"], tile=cfg["tile"])
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_kinds_tile_shapes(kmc, tile):
+    """Particle kinds with the other tile shapes of the search kernel."""
+    w = I.c6_mixture(n=50_000, ic_seed=12, steps=2)
+    for precision in ("fp64", "fp32"):
+        for sm in (kmc.KMC_SEARCH_HALF, kmc.KMC_SEARCH_FULL):
+            run_kinds(kmc, w, 2, precision, search_mode=sm, tile=tile)

@@ -251,13 +251,18 @@ def test_autotune_launch_and_cells(kmc):
     w = I.c5_blobs(n=60_000, steps=2)
     boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0", flags=kmc.KMC_TUNE_LAUNCH, steps=2,
                                    seed=w.seed, precision=kmc.KMC_FP32_SCREEN)
-    print(f"\n[tune] launch: {cfg['search_mode']}/{cfg['block_size']} "
+    print(f"\n[tune] launch: {cfg['search_mode']}/{cfg['block_size']}/tile {cfg['tile']} "
           f"{[round(t['ms_per_step'], 3) for t in tun['tried']]}", flush=True)
+    # organisations x 1 precision, then 2 more tile shapes, then 2 more block sizes
     assert boxes == w.boxes and len(tun["tried"]) == 6
     assert all(np.isfinite(t["ms_per_step"]) for t in tun["tried"])
+    assert {t["tile"] for t in tun["tried"]} == {0, 1, 2}
+    assert {t["block_size"] for t in tun["tried"]} == {128, 256, 512}
+    assert {t["precision"] for t in tun["tried"]} == {kmc.KMC_FP32_SCREEN}
     best = tun["tried"][tun["best"]]
     assert best["ms_per_step"] == min(t["ms_per_step"] for t in tun["tried"])
-    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
+    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"],
+               tile=cfg["tile"])
 
     boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0",
                                    flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_CELLS, steps=2,
@@ -268,7 +273,39 @@ def test_autotune_launch_and_cells(kmc):
     assert len(tun["tried"]) == 24
     assert boxes[0] == kmc.box_with_kappa(w.boxes[0], best["kappa"])
     w.boxes = boxes
-    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"])
+    run_parity(kmc, w, 2, precision="fp32", search_mode=cfg["search_mode"], block_size=cfg["block_size"],
+               tile=cfg["tile"])
+
+
+def test_autotune_precision(kmc):
+    """KMC_TUNE_PRECISION also times both precisions (the partners and
+    states are the same bit for bit); the tuned configuration reproduces the
+    oracle."""
+    w = I.c3_sphere(n=150_000, steps=2)
+    boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0",
+                                   flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_PRECISION, steps=2, seed=w.seed)
+    tried = tun["tried"]
+    print(f"\n[tune] precision: {cfg['precision']} {cfg['search_mode']}/{cfg['block_size']}/tile {cfg['tile']} "
+          f"{[(t['precision'], t['search_mode'], round(t['ms_per_step'], 3)) for t in tried]}", flush=True)
+    assert len(tried) == 8
+    assert {(t["precision"], t["search_mode"]) for t in tried[:4]} == {(0, 0), (0, 1), (1, 0), (1, 1)}
+    best = tried[tun["best"]]
+    assert best["ms_per_step"] == min(t["ms_per_step"] for t in tried)
+    assert cfg["precision"] == best["precision"] and cfg["tile"] == best["tile"]
+    run_parity(kmc, w, 2, precision="fp32" if cfg["precision"] == kmc.KMC_FP32_SCREEN else "fp64",
+               search_mode=cfg["search_mode"], block_size=cfg["block_size"], tile=cfg["tile"])
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("mode", ["half", "full"])
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_tile_shapes(kmc, precision, mode, tile):
+    """The other tile shapes of the search kernel (small LDS chunks; large
+    chunks with fewer waves per SIMD) give the oracle's results."""
+    sm = kmc.KMC_SEARCH_FULL if mode == "full" else kmc.KMC_SEARCH_HALF
+    for w, steps in [(I.c3_sphere(n=150_000, steps=2), 2), (I.c5_blobs(n=60_000, steps=2), 2),
+                     (I.c4_batch(nboxes=6, n_lo=100, n_hi=3000, steps=2), 2)]:
+        run_parity(kmc, w, steps, precision=precision, search_mode=sm, tile=tile)
 
 
 def test_autotune_cache_reuses_the_choice(kmc, tmp_path):
@@ -309,3 +346,24 @@ def test_absorbing_faces(kmc, precision, mode):
     w.boxes = [dataclasses.replace(b, periodic=(False, True, True), absorb=(True, False, False)) for b in w.boxes]
     run_parity(kmc, w, 6, precision=precision, search_mode=sm, use_graph=True)
     assert run_parity.last_stats["absorbed"] > 0
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_history_keeps_exactly_its_capacity(kmc, use_graph):
+    """With history = H the library keeps the last H steps: after exactly H
+    steps all H rows (the oldest included) equal the oracle's, and after
+    more steps the last H do."""
+    w = I.c1_small(steps=8)
+    H = 5
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, history=H, use_graph=use_graph)
+    ref = O.Run(w)
+    want = []
+    for s in range(8):
+        sim.step(1)
+        want.append(ref.step())
+        if s + 1 in (H, 8):
+            hn, hd = sim.history()
+            got = [(int(a), int(b)) for a, b in zip(hn, hd)]
+            assert len(got) == H and got == want[-H:], f"after {s + 1} steps"
+            assert all(n > 0 for n, _ in got)
+    sim.close()
