@@ -620,19 +620,19 @@ __global__ void k_scatter(Plan p)
     bool outside = false;
     double vx = 0.0, vy = 0.0, vz = 0.0;
     if (valid) {
+        const uint32_t c = p.cell[i];
+        uint32_t d = p.start[c] + p.slot[i];
         P64 r;
         r.x = p.A[i];
         r.y = p.A[N + i];
         r.z = p.A[2 * N + i];
-        const uint32_t c = p.cell[i];
-        uint32_t d;
-        const uint32_t lvl = p.adapt_L > 0 ? p.level[c] : 0u;
-        if (lvl) {
+        if (p.adapt_L > 0) {
             // adaptive bins: leaf-sorted inside a split cell
-            const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, r.x, r.y, r.z);
-            d = p.start[c] + p.pool[p.pool_base[c] + code] + p.leaf_slot[i];
-        } else {
-            d = p.start[c] + p.slot[i];
+            const uint32_t lvl = p.level[c];
+            if (lvl) {
+                const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, r.x, r.y, r.z);
+                d = p.start[c] + p.pool[p.pool_base[c] + code] + p.leaf_slot[i];
+            }
         }
         r.vx = vx = p.A[3 * N + i];
         r.vy = vy = p.A[4 * N + i];
