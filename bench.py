@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--adapt", default=None,
                     help="density-adaptive bins L,T (at most L halvings of a cell, split while it holds more than "
                          "T 8^level particles); changes the neighbourhoods, so it is a variant of the workload")
+    ap.add_argument("--block", type=int, default=0, help="threads per block of the streaming kernels (0: 256)")
+    ap.add_argument("--tile", type=int, default=0, help="tile shape of the search kernel (0, 1, 2)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=float, default=None)
     ap.add_argument("--cpu-steps", type=int, default=2)
@@ -356,17 +358,20 @@ def main():
     log(f"[bench] generated {args.workload} N={n} in {time.perf_counter() - t0:.1f} s")
 
     tune = args.autotune or dict(c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
-    paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32")]
+    paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "tuned")]
     if os.environ.get("KMC_BENCH_NO_F32") is not None:
         paths = [p for p in paths if p != "fp32"]
     results, tuned = {}, {}
     for name in paths:
         prec = kmc.KMC_FP64 if name == "fp64" else kmc.KMC_FP32_SCREEN
         search = kmc.KMC_SEARCH_FULL if args.search == "full" else kmc.KMC_SEARCH_HALF
-        block, tile = 0, 0
+        block, tile = args.block, args.tile
         wp = w
-        if tune != "none":
-            flags = kmc.KMC_TUNE_LAUNCH | (kmc.KMC_TUNE_CELLS if tune == "cells" else 0)
+        if tune != "none" or name == "tuned":
+            # "tuned": the autotuner also chooses the precision (both give the
+            # same partners), so the path is never slower than its choice
+            flags = kmc.KMC_TUNE_LAUNCH | (kmc.KMC_TUNE_CELLS if tune == "cells" else 0) | \
+                (kmc.KMC_TUNE_PRECISION if name == "tuned" else 0)
             kinds = None if w.species is None else (w.species, w.radius, w.mass)
             log(f"[bench] {name}: autotune ({tune})")
             nb, cfg, info = kmc.autotune(w.boxes, w.state, device="cuda:0", flags=flags, steps=3, kinds=kinds,
@@ -376,9 +381,11 @@ def main():
             import dataclasses
             wp = dataclasses.replace(w, boxes=nb)
             search, block, tile = cfg["search_mode"], cfg["block_size"], cfg["tile"]
+            prec = cfg["precision"]
             best = info["tried"][info["best"]]
             tuned[name] = dict(search_mode="full" if search == kmc.KMC_SEARCH_FULL else "half",
                                block_size=block, tile=tile, kappa=best["kappa"],
+                               precision="fp32_screen" if prec == kmc.KMC_FP32_SCREEN else "fp64",
                                ms_per_step_tuning=best["ms_per_step"], candidates=len(info["tried"]))
         results[name] = run_path(kmc, wp, prec, args.steps, args.warmup, search, block, tile)
         results[name]["search"] = "full" if search == kmc.KMC_SEARCH_FULL else "half"
@@ -387,13 +394,17 @@ def main():
     identical = None
     if "fp64" in results and "fp32" in results and same_grid:
         identical = results["fp64"]["history"] == results["fp32"]["history"]
+        if "tuned" in results:
+            identical = identical and results["tuned"]["history"] == results["fp64"]["history"]
     golden = golden_check(args.workload, n, results) if (args.dt_rule == "fixed" and tune != "cells"
                                                           and not adapt) else None
     if golden is not None and identical is not None:
         identical = identical and all(golden[k] for k in results)
-    head_key = "fp32" if "fp32" in results else "fp64"
+    head_key = "fp32" if "fp32" in results else ("fp64" if "fp64" in results else "tuned")
     head = results[head_key]
     head_name = "fp32_screen" if head_key == "fp32" else "fp64"
+    if head_key == "tuned":
+        head_name = tuned["tuned"]["precision"]
     search_ms = head["search_kernel_ms"]
     tests = head["pair_tests"]
     achieved = FLOP_PER_PAIR_TEST * tests / (search_ms * 1e-3) / 1e12
@@ -469,6 +480,10 @@ def main():
         line["autotuned"] = tuned
     if "fp64" in results and "fp32" in results:
         line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if "tuned" in results:
+        fixed = [results[k]["value"] for k in ("fp64", "fp32") if k in results]
+        if fixed:
+            line["tuned_over_best_fixed"] = results["tuned"]["value"] / max(fixed)
     if args.copy_calibration:
         # an elementwise kernel that reads and writes 2 GiB each
         src = torch.ones(1 << 29, dtype=torch.float32, device="cuda:0")

@@ -171,15 +171,14 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
         return ptr;
     };
     const size_t N = t.N, C = t.C;
-    // one history row more than kept: each step clears the next row at its
-    // end, so the ring holds the last history_len steps plus that empty row
-    const uint32_t H = history_len(cfg) + 1u;
+    const uint32_t H = history_len(cfg);
     const uint32_t nblk = (uint32_t)((C + kScanTile - 1) / kScanTile);
     const uint32_t cap = cfg.recheck_capacity ? cfg.recheck_capacity : (uint32_t)N;
     p.ctl = (Ctl*)take(sizeof(Ctl));
     p.boxes = (BoxDev*)take(sizeof(BoxDev) * nboxes);
-    p.hist_np = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
-    p.hist_dig = (unsigned long long*)take(sizeof(unsigned long long) * H * kHistLanes);
+    p.hist_np = (unsigned long long*)take(sizeof(unsigned long long) * H);
+    p.hist_dig = (unsigned long long*)take(sizeof(unsigned long long) * H);
+    p.acc = (StepAcc*)take(sizeof(StepAcc) * kAccLanes);
     p.A = (double*)take(sizeof(double) * 6 * N);
     p.B = (P64*)take(sizeof(P64) * N);
     const uint32_t blk = cfg.block_size ? (uint32_t)cfg.block_size : 256u;
@@ -204,7 +203,6 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.partial = (uint32_t*)take(4 * (size_t)(nblk ? nblk : 1));
     p.recheck = (uint32_t*)take(4 * (size_t)(cap ? cap : 1));
     p.ovf = (uint2*)take(sizeof(uint2) * 2 * (N ? N : 1));
-    p.cand_acc = (unsigned long long*)take(sizeof(unsigned long long) * kHistLanes);
     p.adapt_L = cfg.adapt_levels;
     p.adapt_T = cfg.adapt_threshold;
     if (cfg.adapt_levels > 0) {
@@ -531,22 +529,18 @@ int kmc_read_history(kmc_ctx* c, uint64_t* h_npairs, uint64_t* h_digest, uint32_
     hipStream_t s = (hipStream_t)stream;
     const Plan& p = c->plan;
     Ctl ctl;
-    std::vector<unsigned long long> np((size_t)p.H * kHistLanes), dg((size_t)p.H * kHistLanes);
+    std::vector<unsigned long long> np(p.H), dg(p.H);
     hipError_t e = hipMemcpyAsync(&ctl, p.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(np.data(), p.hist_np, np.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(dg.data(), p.hist_dig, dg.size() * 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return KMC_EDEVICE;
-    const uint64_t kept = p.H - 1u;   // the ring's row after the newest is the next step's (cleared)
-    uint64_t avail = ctl.steps_done < kept ? ctl.steps_done : kept;
+    uint64_t avail = ctl.steps_done < p.H ? ctl.steps_done : p.H;
     if (avail > capacity) avail = capacity;
     for (uint64_t k = 0; k < avail; ++k) {
         const uint64_t step = ctl.steps_done - avail + k;
-        const size_t row = (size_t)(step % p.H) * kHistLanes;
-        uint64_t a = 0, d = 0;
-        for (int l = 0; l < kHistLanes; ++l) { a += np[row + l]; d += dg[row + l]; }
-        h_npairs[k] = a;
-        h_digest[k] = d;
+        h_npairs[k] = np[step % p.H];
+        h_digest[k] = dg[step % p.H];
     }
     *count = (uint32_t)avail;
     return KMC_OK;
@@ -600,15 +594,7 @@ int kmc_get_stats(kmc_ctx* c, kmc_stats* out, void* stream)
     out->cells_total = c->plan.C;
     out->rechecks = ctl.rechecks_total;
     out->fallbacks = ctl.fallbacks_total;
-    {
-        unsigned long long acc[kHistLanes];
-        if (hipMemcpyAsync(acc, c->plan.cand_acc, sizeof(acc), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return KMC_EDEVICE;
-        uint64_t tot = 0;
-        for (int l = 0; l < kHistLanes; ++l) tot += acc[l];
-        out->candidates = tot;
-    }
+    out->candidates = ctl.candidates_total;
     out->absorbed = ctl.absorbed_total;
     for (int k = 0; k < 8; ++k) out->ms[k] = c->ms[k];
     out->search_kernel_ms = c->search_kernel_ms;

@@ -275,12 +275,13 @@ __global__ void k_init_ctl(Plan p, unsigned long long step0)
         p.ctl->recheck_count = 0;
         p.ctl->overflow = 0;
         p.ctl->absorbed_total = 0;
+        p.ctl->candidates_total = 0;
         p.ctl->scratch = 0;
     }
-    for (uint32_t k = t; k < (uint32_t)kHistLanes; k += blockDim.x) {
-        p.hist_np[k] = 0;
-        p.hist_dig[k] = 0;
-        p.cand_acc[k] = 0;
+    for (uint32_t k = t; k < (uint32_t)kAccLanes; k += blockDim.x) {
+        p.acc[k].np = 0;
+        p.acc[k].dig = 0;
+        p.acc[k].cand = 0;
     }
     for (uint32_t b = t; b < p.nboxes; b += blockDim.x) p.box_v2[b] = 0ull;
 }
@@ -487,8 +488,11 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
     if (blockIdx.x == 0 && threadIdx.x == 0) p.start[p.C] = p.N;
     if (p.adapt_L > 0) {
         // adaptive bins: this step's split level of every cell from its count;
-        // split cells are listed and claim their leaf tables
+        // split cells are listed and claim their leaf tables (one pair of
+        // atomics per wave: its split cells take consecutive list entries and
+        // pool ranges, in lane order)
         uint64_t lv = 0;
+        uint32_t nsplit = 0, need = 0;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const uint32_t c = base + k;
@@ -496,9 +500,36 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
                 const uint32_t l = split_level(v[k], p.adapt_T, p.adapt_L);
                 lv |= (uint64_t)l << (8 * k);
                 if (l) {
-                    p.refined[atomicAdd(&p.ctl->refined_count, 1u)] = c;
-                    p.pool_base[c] = atomicAdd(&p.ctl->pool_used, (1u << (3 * l)) + 1u);
+                    nsplit += 1u;
+                    need += (1u << (3 * l)) + 1u;
                 }
+            }
+        }
+        const int lane = threadIdx.x & 63;
+        uint32_t xs = nsplit, xn = need;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t ys = __shfl_up(xs, off, 64), yn = __shfl_up(xn, off, 64);
+            if (lane >= off) {
+                xs += ys;
+                xn += yn;
+            }
+        }
+        uint32_t bs = 0, bn = 0;
+        if (lane == 63 && xs) {
+            bs = atomicAdd(&p.ctl->refined_count, xs);
+            bn = atomicAdd(&p.ctl->pool_used, xn);
+        }
+        uint32_t rs = (uint32_t)__shfl((int)bs, 63, 64) + xs - nsplit;
+        uint32_t rn = (uint32_t)__shfl((int)bn, 63, 64) + xn - need;
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            const uint32_t l = (uint32_t)(lv >> (8 * k)) & 0xFFu;
+            if (l) {
+                const uint32_t c = base + k;
+                p.refined[rs++] = c;
+                p.pool_base[c] = rn;
+                rn += (1u << (3 * l)) + 1u;
             }
         }
         if (base + kScanItems <= p.C) {
@@ -1608,7 +1639,7 @@ void k_search_half(Plan p)
     // statistics: pairs the search kept, counted at both particles
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], 2ull * (unsigned long long)c);
+    if (lane == 0 && c) atomicAdd(&p.acc[blockIdx.x % kAccLanes].cand, 2ull * (unsigned long long)c);
 }
 
 // Full-neighbourhood variant of the search (KMC_SEARCH_FULL): every
@@ -1719,7 +1750,7 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
         uint64_t c = Pol::kScreen ? best.screened : best.accepted;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-        if (lane == 0 && c) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)c);
+        if (lane == 0 && c) atomicAdd(&p.acc[blockIdx.x % kAccLanes].cand, (unsigned long long)c);
     }
 }
 
@@ -1996,12 +2027,20 @@ __device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, 
     if (STATS) {
 #pragma unroll
         for (int sft = 32; sft > 0; sft >>= 1) nstat += __shfl_xor(nstat, sft, 64);
-        if (lane == 0 && nstat) atomicAdd(&p.cand_acc[blockIdx.x % kHistLanes], (unsigned long long)nstat);
+        if (lane == 0 && nstat) atomicAdd(&p.acc[blockIdx.x % kAccLanes].cand, (unsigned long long)nstat);
     }
 }
 
+// Waves per SIMD of the adaptive-bin search: the FP32 variant is held to
+// four (at five it spills; measured 9.5 -> 8.5 ms on the blob gas).
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
+constexpr int adapt_waves()
+{
+    return Pol::kScreen ? 4 : Pol::kFullWaves;
+}
+
+template <class Pol>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(adapt_waves<Pol>())))
 void k_search_adapt(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -2012,7 +2051,7 @@ void k_search_adapt(Plan p)
 // The whole-step FP64 search of the particles k_search_adapt takes (see
 // k_fallback_full).
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(adapt_waves<Pol>())))
 void k_fallback_adapt(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -2038,7 +2077,7 @@ __global__ void k_distribute_overflow(Plan p)
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && n)
-        atomicAdd(&p.cand_acc[0], 2ull * (unsigned long long)n);
+        atomicAdd(&p.acc[0].cand, 2ull * (unsigned long long)n);
 }
 
 // Wave-aggregated append of this lane's particle to the FP64 recheck list
@@ -2318,27 +2357,41 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(K ? 1 : 8)
     if ((threadIdx.x & 63) == 0 && lm) atomicAdd(&p.ctl->absorbed_total, (unsigned long long)__popcll(lm));
     block_sum2(my_np, my_dig, lds);
     if (threadIdx.x == 0 && my_np != 0) {
-        const size_t row = (size_t)(p.ctl->steps_done % p.H) * kHistLanes + (blockIdx.x % kHistLanes);
-        atomicAdd(&p.hist_np[row], (unsigned long long)my_np);
-        atomicAdd(&p.hist_dig[row], (unsigned long long)my_dig);
+        StepAcc& a = p.acc[blockIdx.x % kAccLanes];
+        atomicAdd(&a.np, (unsigned long long)my_np);
+        atomicAdd(&a.dig, (unsigned long long)my_dig);
     }
 }
 
-// End of step: advance the step counters, fold the screen statistics and
-// clear the next history row.
-__global__ void k_advance(Plan p)
+// End of step (one block of kAdvanceThreads): fold this step's partial sums
+// into its history row and the running candidate count, clear them, and
+// advance the step counters.
+constexpr uint32_t kAdvanceThreads = 1024;
+
+__global__ __launch_bounds__(kAdvanceThreads) void k_advance(Plan p)
 {
-    const unsigned long long next = p.ctl->steps_done + 1;
-    const size_t row = (size_t)(next % p.H) * kHistLanes;
-    for (uint32_t k = threadIdx.x; k < (uint32_t)kHistLanes; k += blockDim.x) {
-        p.hist_np[row + k] = 0;
-        p.hist_dig[row + k] = 0;
+    __shared__ uint64_t lds[32];
+    uint64_t np = 0, dig = 0, cand = 0, z = 0;
+    for (uint32_t k = threadIdx.x; k < (uint32_t)kAccLanes; k += blockDim.x) {
+        StepAcc& a = p.acc[k];
+        np += a.np;
+        dig += a.dig;
+        cand += a.cand;
+        a.np = 0;
+        a.dig = 0;
+        a.cand = 0;
     }
+    block_sum2(np, dig, lds);
     __syncthreads();
+    block_sum2(cand, z, lds);
     if (threadIdx.x == 0) {
+        const unsigned long long done = p.ctl->steps_done;
+        p.hist_np[done % p.H] = np;
+        p.hist_dig[done % p.H] = dig;
+        p.ctl->candidates_total += cand;
         p.ctl->rechecks_total += p.ctl->recheck_count;
         p.ctl->fallbacks_total += p.ctl->overflow ? 1ull : 0ull;
-        p.ctl->steps_done = next;
+        p.ctl->steps_done = done + 1;
         p.ctl->step += 1;
     }
 }
@@ -2479,7 +2532,7 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         if (p.nspecies > 0) k_resolve<true><<<gN, b, 0, s>>>(p);
         else k_resolve<false><<<gN, b, 0, s>>>(p);
     }
-    k_advance<<<1, 64, 0, s>>>(p);
+    k_advance<<<1, kAdvanceThreads, 0, s>>>(p);
     mark(KMC_PHASE_COUNT);
     return hipGetLastError();
 }

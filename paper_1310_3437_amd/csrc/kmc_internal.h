@@ -13,8 +13,10 @@ namespace kmc {
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanBlock * kScanItems;
-// Partial sums per history row (spreads the per-step count/digest atomics).
-constexpr int kHistLanes = 64;
+// Per-step accumulators of the collision count, the digest and the recorded
+// candidates: one 128-byte line each, so the per-block atomics of the search
+// and the resolve spread over this many cache lines (k_advance folds them).
+constexpr int kAccLanes = 4096;
 // Candidates the search records per particle before the particle falls
 // back to a full search.
 constexpr int kSlots = 8;
@@ -59,6 +61,11 @@ struct alignas(16) P64 {
     double x, y, z, vx, vy, vz;
 };
 
+struct alignas(128) StepAcc {
+    unsigned long long np, dig, cand;
+    unsigned long long pad_[13];
+};
+
 // Candidate list entry: one 16-byte store per posted pair.
 struct alignas(16) SlotEntry {
     double key;      // c2 / g2 of the pair (the same from both sides)
@@ -74,6 +81,7 @@ struct Ctl {
     unsigned long long fallbacks_total; // steps that took the whole-step FP64 search
     unsigned long long scratch;         // target of host-requested reductions
     unsigned long long absorbed_total;  // particles absorbed by absorbing faces so far
+    unsigned long long candidates_total;// pairs the search recorded, summed over steps
     unsigned int recheck_count;         // this step's recheck list length
     unsigned int overflow;              // this step's flag for the whole-step FP64 search
     unsigned int ovf_count;             // this step's overflow pair list length
@@ -97,8 +105,9 @@ struct alignas(16) ScreenBounds {
 struct Plan {
     Ctl* ctl;
     BoxDev* boxes;
-    unsigned long long* hist_np;   // [history][kHistLanes]
-    unsigned long long* hist_dig;  // [history][kHistLanes]
+    unsigned long long* hist_np;   // [history]: collision count of each step (a ring)
+    unsigned long long* hist_dig;  // [history]: digest of each step
+    StepAcc* acc;                  // [kAccLanes]: this step's partial sums
     double* A;                     // current state, 6*N SoA (previous cell order)
     P64* B;                        // cell-sorted copy of the current state (records)
     float* vmax_part;              // per scatter block: max |v_k| of its particles this step
@@ -119,7 +128,6 @@ struct Plan {
     uint32_t* partial;             // scan block sums
     uint32_t* recheck;             // sorted indices to re-search in full FP64
     uint2* ovf;                    // pairs a search lane found beyond its register slots
-    unsigned long long* cand_acc;  // kHistLanes accumulators of recorded candidates
     unsigned long long* v2_part;   // adaptive dt: per scatter block, max |v|^2 (FP64 bits) of
                                    // its particles in the box of its first particle
     unsigned long long* box_v2;    // adaptive dt: per box, max |v|^2 of the other particles
