@@ -1490,43 +1490,6 @@ struct PolF32 {
             }
         }
     }
-    // adaptive bins: as PolF64::scan_adapt, every pair the screen keeps
-    // decided in FP64 with the candidate's image
-    __device__ static void scan_adapt(const Plan& p, const Lds& l, const uint32_t* lid, const uint32_t*,
-                                      const uint32_t* lw, uint32_t n, uint32_t u, uint32_t kk, uint32_t io,
-                                      const Own& o, const BoxDev& B, const Group& g, Best& best)
-    {
-        const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
-        for (uint32_t t = u; t < n; t += kk) {
-            const float4 qa = l.a[t];
-            const float4 qb = l.b[t];
-            const uint32_t j = __float_as_uint(qb.w);
-            const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
-            const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
-            const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
-            const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
-            const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const uint32_t kj = K ? __float_as_uint(qb.z) : 0u;
-            const float kd = K ? l.kd2[o.row + kj] : kD2;
-            const float mb = fmaf(-tb1, g2, b);
-            const float m2 = fmaf(-kdt, g2, -b);
-            const float m3 = fmaf(rr - kd, g2, -(b * b));
-            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != io)) {
-                const P64 me = p.B[io], q = p.B[j];
-                double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
-                const uint32_t w = lw[t];
-                if (w != kNoImage) {
-                    const int wx = (int)(w & 3u) - 1, wy = (int)((w >> 2) & 3u) - 1, wz = (int)((w >> 4) & 3u) - 1;
-                    if (wx != 0) rx6 = rx6 + (double)wx * B.L[0];
-                    if (wy != 0) ry6 = ry6 + (double)wy * B.L[1];
-                    if (wz != 0) rz6 = rz6 + (double)wz * B.L[2];
-                }
-                const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-                best.screened += 1u;
-                if (accept(pq, K ? p.sp_D2[o.row + kj] : B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[t], j);
-            }
-        }
-    }
 };
 
 template <class Pol>
@@ -2031,16 +1994,8 @@ __device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, 
     }
 }
 
-// Waves per SIMD of the adaptive-bin search: the FP32 variant is held to
-// four (at five it spills; measured 9.5 -> 8.5 ms on the blob gas).
 template <class Pol>
-constexpr int adapt_waves()
-{
-    return Pol::kScreen ? 4 : Pol::kFullWaves;
-}
-
-template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(adapt_waves<Pol>())))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
 void k_search_adapt(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -2051,7 +2006,7 @@ void k_search_adapt(Plan p)
 // The whole-step FP64 search of the particles k_search_adapt takes (see
 // k_fallback_full).
 template <class Pol>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(adapt_waves<Pol>())))
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(Pol::kFullWaves)))
 void k_fallback_adapt(Plan p)
 {
     __shared__ typename Pol::Lds lds;
@@ -2503,13 +2458,11 @@ hipError_t launch_step(const Plan& p, hipStream_t s, hipEvent_t* ev)
         }
     }
     if (p.N > 0 && p.adapt_L > 0) {
-        if (p.precision == KMC_FP32_SCREEN) {
-            if (p.nspecies > 0) k_search_adapt<PolF32<true>><<<gW, 64, 0, s>>>(p);
-            else k_search_adapt<PolF32<false>><<<gW, 64, 0, s>>>(p);
-        } else {
-            if (p.nspecies > 0) k_search_adapt<PolF64<true>><<<gW, 64, 0, s>>>(p);
-            else k_search_adapt<PolF64<false>><<<gW, 64, 0, s>>>(p);
-        }
+        // the particles next to split cells: plain FP64 in both precisions
+        // (their groups are leaves of a few particles, where the screen's
+        // conversions and FP64 decisions cost more than they save)
+        if (p.nspecies > 0) k_search_adapt<PolF64<true>><<<gW, 64, 0, s>>>(p);
+        else k_search_adapt<PolF64<false>><<<gW, 64, 0, s>>>(p);
     }
     mark(KMC_PHASE_FINISH);
     if (p.N > 0 && !full) {

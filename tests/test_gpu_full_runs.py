@@ -4,8 +4,9 @@ and step counts, against the oracle's record of the same runs
 with the CPU oracle alone).
 
 Every step: the partner array (the partner id of every particle id, -1 for
-none) must hash to the oracle's, and the step's collision count and digest
-must be the oracle's.  After the last step the (6, N) FP64 state in id order
+none) must hash to the oracle's, the ordered pair tests of the 27-cell
+search must be the oracle's, and the step's collision count and digest must
+be the oracle's.  After the last step the (6, N) FP64 state in id order
 must hash to the oracle's (bit-exact; the sampled particles stored beside the
 hash give the size of any difference).  Both precisions run; the headline
 workload (c3_sphere at N = 1e8) runs in graph-replay mode, as the benchmark
@@ -61,6 +62,7 @@ def _check_run(kmc, w, g, precision, **cfg):
         assert p.dtype == np.int32
         if _sha(p.astype("<i4")) != e["partners_sha256"]:
             raise AssertionError(f"{name} {precision}: partner array differs from the oracle's at step {e['step']}")
+        assert sim.pair_tests() == e["pair_tests"], f"{name} {precision}: pair tests differ at step {e['step']}"
     hn, hd = sim.history()
     got = [(int(a), int(b)) for a, b in zip(hn, hd)]
     want = [(e["npairs"], int(e["digest"], 16)) for e in g["per_step"]]
@@ -95,3 +97,11 @@ def test_c4_batch_256_boxes_50_steps(kmc):
     w = _workload(g)
     _check_run(kmc, w, g, "fp32", use_graph=True)
     _check_run(kmc, w, g, "fp64", search_mode=kmc.KMC_SEARCH_FULL)
+
+
+@pytest.mark.timeout(900)
+def test_c3_sphere_1e8_20_steps_graph_replay(kmc):
+    g = _golden("c3_sphere")
+    w = _workload(g)
+    for precision in ("fp32", "fp64"):
+        _check_run(kmc, w, g, precision, use_graph=True)
