@@ -19,7 +19,13 @@ of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
                     [--workload c3_sphere|c2_shock|c4_batch|c5_blobs|c6_mixture] [--dt-rule adaptive]
-                    [--search half|full] [--autotune none|launch|cells] [--ppc-sweep]
+                    [--search half|full] [--autotune none|launch|cells] [--adapt L,T]
+                    [--paths fp64,fp32,tuned] [--block B] [--tile 0|1|2] [--ppc-sweep]
+
+`--paths ... tuned` adds a path whose precision, search organisation, tile
+shape and block size the autotuner picks on the workload itself (both
+precisions give the same partners); `tuned_over_best_fixed` compares it with
+the faster fixed precision.
 
 The other workloads (shock tube, 256-box batch, Gaussian blobs, mixture)
 print the same line for their own configuration; the headline is c3_sphere.
