@@ -19,6 +19,7 @@ import os
 import numpy as np
 import pytest
 
+from oracle import oracle as O
 from paper_1310_3437_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -105,3 +106,77 @@ def test_c3_sphere_1e8_20_steps_graph_replay(kmc):
     w = _workload(g)
     for precision in ("fp32", "fp64"):
         _check_run(kmc, w, g, precision, use_graph=True)
+
+
+@pytest.mark.timeout(900)
+def test_c5_blobs_1e7_3_steps(kmc):
+    """The uneven gas (up to 1.7e3 particles per cell): the full search in
+    both precisions (the FP32 screen in graph replay), and the half search,
+    whose candidate lists overflow there (its whole-step FP64 search then
+    decides the step)."""
+    g = _golden("c5_blobs")
+    w = _workload(g)
+    _check_run(kmc, w, g, "fp32", search_mode=kmc.KMC_SEARCH_FULL, use_graph=True)
+    _check_run(kmc, w, g, "fp64", search_mode=kmc.KMC_SEARCH_FULL)
+    _check_run(kmc, w, g, "fp32")
+
+
+def _sampled_every_step(kmc, w, steps, precision, **cfg):
+    """Run `steps` steps; before each, read the state back (id order) and
+    evaluate the oracle's step at sampled particles of it (random ones, ones
+    in cells of more than 64 particles, and this step's colliders): their
+    partners and post-step states must equal the GPU's, and the step's
+    collision count must follow from the partner array."""
+    import torch
+    prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+    print(f"\n[sampled] {w.name} N={w.n} steps={steps} {precision} {cfg}", flush=True)
+    sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, kinematics=w.kinematics, precision=prec,
+                  history=max(64, steps), **cfg)
+    box = w.boxes[0]
+    n = w.n
+    ids = np.arange(n, dtype=np.uint32)
+    idx = np.arange(n)
+    rng = np.random.default_rng(11)
+    inv_h = np.array(box.inv_h)[:, None]
+    lo = np.array(box.lo)[:, None]
+    pre = sim.state().cpu().numpy()
+    counts = []
+    for s in range(steps):
+        sim.step(1)
+        p = sim.partners().cpu().numpy()
+        has = p >= 0
+        mutual = np.zeros(n, dtype=bool)
+        mutual[has] = p[p[has]] == idx[has]
+        counts.append(int((mutual & (idx < p)).sum()))
+        cells = np.clip(np.floor((pre[0:3] - lo) * inv_h).astype(np.int64), 0, np.array(box.ncell)[:, None] - 1)
+        lin = cells[0] + box.ncell[0] * (cells[1] + box.ncell[1] * cells[2])
+        dense = np.flatnonzero(np.bincount(lin, minlength=box.ncells)[lin] > 64)
+        col = np.flatnonzero(mutual)
+        sel = np.unique(np.concatenate([rng.choice(n, 500, replace=False),
+                                        rng.choice(dense, min(500, dense.size), replace=False),
+                                        rng.choice(col, min(500, col.size), replace=False)])).astype(np.int64)
+        ref_p, ref_s = O.step_sampled(box, pre, ids, s, sel, seed=w.seed, kinematics=w.kinematics)
+        bad = np.flatnonzero(p[sel] != ref_p)
+        assert bad.size == 0, f"step {s}: {bad.size} of {sel.size} sampled partners differ, first ids {sel[bad[:5]]}"
+        st = sim.state()
+        got = st[:, torch.as_tensor(sel, device=st.device)].cpu().numpy()
+        assert np.array_equal(got, ref_s), f"step {s}: sampled post-step states differ"
+        pre = st.cpu().numpy()
+        if s % 10 == 9:
+            print(f"[sampled] step {s + 1}: {sel.size} sampled particles identical", flush=True)
+    hn, _ = sim.history()
+    assert [int(a) for a in hn] == counts
+    stats = sim.stats()
+    sim.close()
+    print(f"[sampled] ok: {sum(counts)} collisions over {steps} steps, fallbacks {stats['fallbacks']}", flush=True)
+
+
+@pytest.mark.timeout(900)
+def test_c5_blobs_1e7_50_steps_sampled(kmc):
+    """The uneven gas over its full 50 steps (the whole-run record above
+    holds 3: the oracle needs ten minutes per step there), checked every step
+    at about 1500 sampled particles, FP32 screen in graph replay and FP64,
+    with the full search the autotuner picks for it."""
+    w = I.c5_blobs(steps=50)
+    _sampled_every_step(kmc, w, 50, "fp32", search_mode=kmc.KMC_SEARCH_FULL, use_graph=True)
+    _sampled_every_step(kmc, w, 50, "fp64", search_mode=kmc.KMC_SEARCH_FULL)
