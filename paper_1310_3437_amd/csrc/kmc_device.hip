@@ -1809,6 +1809,70 @@ __device__ __forceinline__ void neighbour_leaves(const Plan& p, const BoxDev& B,
         }
 }
 
+// The same ranges in two parts, for a wave that lists the neighbourhoods of
+// several leaves of one cell in turn: the neighbour cell's data (its index,
+// level, start and leaf-table offset, loaded together) kept across the
+// leaves, then per leaf the touching runs, which only load leaf-table
+// entries (and nothing at all when only counted).
+struct NbCell {
+    int32_t lvl;       // split level; -1: the neighbour cell does not exist
+    int32_t qw[3];     // its cell coordinates with the periodic image (q + w n)
+    uint32_t code;     // image and cell offset (as neighbour_leaves reports them)
+    uint32_t s0, s1;   // start[cell], start[cell + 1]
+    uint32_t pb;       // pool_base[cell] (split cells)
+};
+
+__device__ __forceinline__ void nb_cell_load(const Plan& p, const BoxDev& B, const int c[3], int dx, int dy, int dz,
+                                             NbCell& nc)
+{
+    const int d[3] = {dx, dy, dz};
+    int q[3], w[3];
+    nc.lvl = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q[a] = c[a] + d[a];
+        w[a] = 0;
+        if (q[a] < 0) { if (!B.periodic[a]) return; q[a] += B.nc[a]; w[a] = -1; }
+        else if (q[a] >= B.nc[a]) { if (!B.periodic[a]) return; q[a] -= B.nc[a]; w[a] = 1; }
+        nc.qw[a] = q[a] + w[a] * B.nc[a];
+    }
+    nc.code = wcode(w[0], w[1], w[2]) | ((uint32_t)wcode(dx, dy, dz) << 6);
+    const uint32_t cell = B.coff + (uint32_t)q[0] + (uint32_t)B.nc[0] * ((uint32_t)q[1] + (uint32_t)B.nc[1] * (uint32_t)q[2]);
+    nc.lvl = (int)p.level[cell];
+    nc.s0 = p.start[cell];
+    nc.s1 = p.start[cell + 1];
+    nc.pb = p.pool_base[cell];
+}
+
+// The leaves of a cached neighbour cell that touch the leaf [lo, hi]: their
+// index box jlo..jhi per axis, and the number of runs they form in the
+// cell's leaf order (one per (jy, jz) row of a split cell, one for an
+// unsplit cell, 0 when none touches).
+__device__ __forceinline__ uint32_t nb_leaf_box(const Plan& p, const NbCell& nc, const int lo[3], const int hi[3],
+                                                int jlo[3], int jhi[3])
+{
+    if (nc.lvl < 0) return 0u;
+    const int L = p.adapt_L;
+    const int sh = L - nc.lvl, r = 1 << nc.lvl;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // the neighbour's lower face on the finest grid, with its image
+        const long long b0 = (long long)nc.qw[a] << L;
+        jlo[a] = (int)max(0ll, ((long long)lo[a] - b0 - 1) >> sh);
+        jhi[a] = (int)min((long long)(r - 1), ((long long)hi[a] + 1 - b0) >> sh);
+        if (jlo[a] > jhi[a]) return 0u;
+    }
+    if (nc.lvl == 0) return 1u;
+    return (uint32_t)(jhi[1] - jlo[1] + 1) * (uint32_t)(jhi[2] - jlo[2] + 1);
+}
+
+// One neighbour cell of a group as the wave's lanes read it when they list
+// the runs in parallel.
+struct NbBox {
+    int32_t jlo0, jhi0, jlo1, ny, jlo2, lvl;
+    uint32_t s0, s1, pb, code;
+};
+
 // A particle's cell (c) and leaf ([lo, hi] in finest indices) under adaptive
 // bins, from its position; returns the linear cell.
 __device__ __forceinline__ uint32_t leaf_of(const Plan& p, const BoxDev& B, double x, double y, double z, int c[3],
@@ -1839,6 +1903,8 @@ constexpr int kRangeBatch = 128;
 
 template <int W>
 struct AdaptLds {
+    NbBox nb[27];                    // the group's neighbour cells (runs of touching leaves)
+    uint32_t noff[27];               // exclusive prefix of their run counts
     uint32_t rs[kRangeBatch];        // range starts (sorted index)
     uint32_t rc[kRangeBatch];        // range codes (image, cell offset)
     uint32_t rp[kRangeBatch + 1];    // exclusive prefix of the range sizes
@@ -1876,6 +1942,12 @@ __device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, 
     Best best;
     uint64_t nstat = 0;
     uint64_t remaining = __ballot(alive);
+    // lanes 0..26: neighbour cell (lane % 3 - 1, lane / 3 % 3 - 1, lane / 9 - 1)
+    // of the cell of the current group, kept while the groups stay in it
+    const int ndx = lane % 3 - 1, ndy = (lane / 3) % 3 - 1, ndz = lane / 9 - 1;
+    NbCell nbc;
+    nbc.lvl = -1;
+    uint32_t nb_of = 0xFFFFFFFFu;
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t gcell = (uint32_t)__builtin_amdgcn_readlane((int)cell, lead);
@@ -1911,10 +1983,16 @@ __device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, 
         best.accepted = 0u;
         best.screened = 0u;
         // ranges of the touching leaves: lanes 0..26 take one neighbour cell each
+        if (gcell != nb_of) {
+            if (lane < 27) nb_cell_load(p, B, gc, ndx, ndy, ndz, nbc);
+            nb_of = gcell;
+        }
+        // per neighbour cell the box of touching leaves and its number of
+        // runs, published; then the lanes list the runs f = lane, lane + 64,
+        // ... of the flat sequence (cell by cell, rows jz-major) in parallel
+        int bjlo[3] = {0, 0, 0}, bjhi[3] = {0, 0, 0};
         uint32_t nr = 0;
-        if (lane < 27)
-            neighbour_leaves(p, B, gc, glo, ghi, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1,
-                             [&](uint32_t, uint32_t, uint32_t) { ++nr; });
+        if (lane < 27) nr = nb_leaf_box(p, nbc, glo, ghi, bjlo, bjhi);
         uint32_t off = nr;
 #pragma unroll
         for (int sft = 1; sft < 64; sft <<= 1) {
@@ -1923,19 +2001,43 @@ __device__ __forceinline__ void search_adapt_tile(const Plan& p, uint32_t tile, 
         }
         const uint32_t R = (uint32_t)__shfl((int)off, 63, 64);
         off -= nr;
+        if (lane < 27) {
+            NbBox& nx = al.nb[lane];
+            nx.jlo0 = bjlo[0];
+            nx.jhi0 = bjhi[0];
+            nx.jlo1 = bjlo[1];
+            nx.ny = bjhi[1] - bjlo[1] + 1;
+            nx.jlo2 = bjlo[2];
+            nx.lvl = nbc.lvl;
+            nx.s0 = nbc.s0;
+            nx.s1 = nbc.s1;
+            nx.pb = nbc.pb;
+            nx.code = nbc.code;
+            al.noff[lane] = off;
+        }
+        __syncthreads();
         for (uint32_t rb = 0; rb < R; rb += (uint32_t)kRangeBatch) {
             const uint32_t nb = min((uint32_t)kRangeBatch, R - rb);
-            if (lane < 27 && nr) {
-                uint32_t k = off;
-                neighbour_leaves(p, B, gc, glo, ghi, lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1,
-                                 [&](uint32_t s, uint32_t e, uint32_t cd) {
-                                     if (k >= rb && k < rb + nb) {
-                                         al.rs[k - rb] = s;
-                                         al.rc[k - rb] = cd;
-                                         al.rp[k - rb] = e - s;   // size, turned into the prefix below
-                                     }
-                                     ++k;
-                                 });
+            for (uint32_t f = rb + (uint32_t)lane; f < rb + nb; f += 64u) {
+                // the neighbour cell d of run f: the last with noff[d] <= f
+                uint32_t d = 0;
+#pragma unroll
+                for (uint32_t step = 16; step > 0; step >>= 1)
+                    if (d + step < 27u && al.noff[d + step] <= f) d += step;
+                const NbBox& nx = al.nb[d];
+                const uint32_t k = f - al.noff[d];
+                uint32_t s0 = nx.s0, e0 = nx.s1;
+                if (nx.lvl > 0) {
+                    const uint32_t r = 1u << nx.lvl;
+                    const uint32_t jy = (uint32_t)nx.jlo1 + k % (uint32_t)nx.ny;
+                    const uint32_t jz = (uint32_t)nx.jlo2 + k / (uint32_t)nx.ny;
+                    const uint32_t* t = p.pool + nx.pb + r * (jy + r * jz);
+                    s0 = nx.s0 + t[nx.jlo0];
+                    e0 = nx.s0 + t[nx.jhi0 + 1];
+                }
+                al.rs[f - rb] = s0;
+                al.rc[f - rb] = nx.code;
+                al.rp[f - rb] = e0 - s0;   // size, turned into the prefix below
             }
             __syncthreads();
             // exclusive prefix of the nb sizes: two per lane
