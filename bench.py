@@ -19,7 +19,7 @@ of the same workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N] [--no-cpu]
                     [--workload c3_sphere|c2_shock|c4_batch|c5_blobs|c6_mixture] [--dt-rule adaptive]
-                    [--search half|full] [--autotune none|launch|cells] [--adapt L,T]
+                    [--search half|full] [--autotune none|launch|cells] [--adapt L,T|L,auto]
                     [--paths fp64,fp32,tuned] [--block B] [--tile 0|1|2] [--ppc-sweep]
 
 `--paths ... tuned` adds a path whose precision, search organisation, tile
@@ -325,7 +325,8 @@ def main():
                          "default cells for c4_batch, launch for c5_blobs, none otherwise")
     ap.add_argument("--adapt", default=None,
                     help="density-adaptive bins L,T (at most L halvings of a cell, split while it holds more than "
-                         "T 8^level particles); changes the neighbourhoods, so it is a variant of the workload")
+                         "T 8^level particles; T = auto: chosen by the autotuner); changes the neighbourhoods, so "
+                         "it is a variant of the workload")
     ap.add_argument("--block", type=int, default=0, help="threads per block of the streaming kernels (0: 256)")
     ap.add_argument("--tile", type=int, default=0, help="tile shape of the search kernel (0, 1, 2)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -356,12 +357,35 @@ def main():
         raise SystemExit(f"bench.py: unknown workload {args.workload}")
     n_arg = args.n if args.n is not None else full[args.workload]
     t0 = time.perf_counter()
-    adapt = tuple(int(x) for x in args.adapt.split(",")) if args.adapt else None
-    if adapt:
+    adapt, adapt_auto = None, False
+    if args.adapt:
+        lv, th = args.adapt.split(",")
+        adapt_auto = th == "auto"
+        adapt = (int(lv), 8 if adapt_auto else int(th))
         args.search = "full"
     w, desc = workload(args.workload, int(n_arg) if n_arg else None, args.dt_rule, adapt)
     n = w.n
     log(f"[bench] generated {args.workload} N={n} in {time.perf_counter() - t0:.1f} s")
+    adapt_tuning = None
+    if adapt_auto:
+        # the autotuner picks the adaptive-bin threshold (a grid choice: it
+        # changes the neighbourhoods), then every path runs with it
+        kinds = None if w.species is None else (w.species, w.radius, w.mass)
+        log("[bench] autotune of the adaptive-bin threshold")
+        _, cfg, info = kmc.autotune(w.boxes, w.state, device="cuda:0", steps=3, kinds=kinds,
+                                    flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_PRECISION | kmc.KMC_TUNE_ADAPT,
+                                    seed=w.seed, dt_rule=w.dt_rule, dt_factor=w.dt_factor if w.dt_rule else 0.0,
+                                    search_mode=kmc.KMC_SEARCH_FULL, adapt_levels=w.adapt_levels,
+                                    adapt_threshold=w.adapt_threshold)
+        w.adapt_threshold = int(cfg["adapt_threshold"])
+        best_by_t = {}
+        for t in info["tried"]:
+            if t["ms_per_step"] == t["ms_per_step"]:
+                th = t["adapt_threshold"]
+                best_by_t[th] = min(best_by_t.get(th, float("inf")), t["ms_per_step"])
+        adapt_tuning = dict(threshold=w.adapt_threshold, best_ms_per_step_by_threshold=best_by_t,
+                            candidates=len(info["tried"]))
+        desc = desc.replace("than 8 x 8^level", f"than {w.adapt_threshold} x 8^level (threshold autotuned)")
 
     tune = args.autotune or dict(c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
     paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "tuned")]
@@ -486,6 +510,8 @@ def main():
         line["autotuned"] = tuned
     if "fp64" in results and "fp32" in results:
         line["fp32_over_fp64"] = results["fp32"]["value"] / results["fp64"]["value"]
+    if adapt_tuning is not None:
+        line["adapt_autotuned"] = adapt_tuning
     if "tuned" in results:
         fixed = [results[k]["value"] for k in ("fp64", "fp32") if k in results]
         if fixed:

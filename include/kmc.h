@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define KMC_ABI_VERSION 4
+#define KMC_ABI_VERSION 5
 
 typedef enum {
     KMC_OK = 0,
@@ -370,14 +370,21 @@ int kmc_get_stats(kmc_ctx* ctx, kmc_stats* out, void* stream);
  *                    part of the partner criteria (Section 1: partners are
  *                    searched in the neighbouring bins), so this changes the
  *                    results: the caller must use the returned boxes
- *                    everywhere (including any reference it compares with). */
-enum { KMC_TUNE_LAUNCH = 1, KMC_TUNE_CELLS = 2, KMC_TUNE_PRECISION = 4 };
+ *                    everywhere (including any reference it compares with);
+ *   KMC_TUNE_ADAPT   with density-adaptive bins (cfg->adapt_levels > 0,
+ *                    else KMC_EINVAL) also their threshold: adapt_threshold
+ *                    in {4, 8, 16, 32}.  The bins are part of the partner
+ *                    criteria as well, so the caller must use the returned
+ *                    out_cfg->adapt_threshold everywhere. */
+enum { KMC_TUNE_LAUNCH = 1, KMC_TUNE_CELLS = 2, KMC_TUNE_PRECISION = 4, KMC_TUNE_ADAPT = 8 };
 
 /* The candidates are searched one coordinate at a time, for every cell grid
- * (the given one, or each kappa with KMC_TUNE_CELLS): first the precisions
- * (with KMC_TUNE_PRECISION) times the search organisations, then the other
- * tile shapes, then the other block sizes (128, 512), each stage keeping the
- * fastest so far.  At most KMC_TUNE_MAX candidates are timed. */
+ * (the given one, or each kappa with KMC_TUNE_CELLS) and every adaptive-bin
+ * threshold (the given one, or each candidate with KMC_TUNE_ADAPT): first the
+ * precisions (with KMC_TUNE_PRECISION) times the search organisations (only
+ * the full search with adaptive bins), then the other tile shapes, then the
+ * other block sizes (128, 512), each stage keeping the fastest so far.  At
+ * most KMC_TUNE_MAX candidates are timed (later ones are not tried). */
 #define KMC_TUNE_MAX 64
 typedef struct kmc_tuning {
     uint32_t ntried;                 /* candidates timed                           */
@@ -388,20 +395,23 @@ typedef struct kmc_tuning {
     double kappa[KMC_TUNE_MAX];      /* cell-edge factor (0: the given grid)       */
     int32_t precision[KMC_TUNE_MAX];
     int32_t tile[KMC_TUNE_MAX];
+    uint32_t adapt_threshold[KMC_TUNE_MAX]; /* adaptive-bin threshold (0: uniform grid) */
 } kmc_tuning;
 
 /* Time every candidate over `steps` steps (after one untimed step) from the
  * same input, choose the fastest, and write the chosen boxes and
  * configuration to out_boxes (nboxes entries; equal to `boxes` unless
  * KMC_TUNE_CELLS) and *out_cfg (cfg with search_mode, tile, block_size and,
- * with KMC_TUNE_PRECISION, precision set; the other fields are copied).
+ * with KMC_TUNE_PRECISION, precision and, with KMC_TUNE_ADAPT,
+ * adapt_threshold set; the other fields are copied).
  *   d_state, d_workspace  as for kmc_init; the workspace must hold the
  *                    largest candidate (kmc_workspace_bytes of the boxes
  *                    with kappa = 1, block_size 64 and, with
- *                    KMC_TUNE_PRECISION, precision KMC_FP32_SCREEN suffices);
- *                    candidates that do not fit are skipped;
- *   flags            KMC_TUNE_LAUNCH, KMC_TUNE_CELLS and/or KMC_TUNE_PRECISION
- *                    (0 = LAUNCH).
+ *                    KMC_TUNE_PRECISION, precision KMC_FP32_SCREEN and, with
+ *                    KMC_TUNE_ADAPT, adapt_threshold 4 suffices); candidates
+ *                    that do not fit are skipped;
+ *   flags            KMC_TUNE_LAUNCH, KMC_TUNE_CELLS, KMC_TUNE_PRECISION
+ *                    and/or KMC_TUNE_ADAPT (0 = LAUNCH).
  * d_state is only read.  Synchronises `stream`.  Errors as kmc_init, and
  * KMC_ENOMEM when no candidate fits. */
 int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, const double* d_state,

@@ -632,7 +632,9 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     if (rc != KMC_OK) return rc;
     if (t.N > 0 && !d_state) return KMC_EINVAL;
     if (flags == 0) flags = KMC_TUNE_LAUNCH;
-    if (flags & ~(uint32_t)(KMC_TUNE_LAUNCH | KMC_TUNE_CELLS | KMC_TUNE_PRECISION)) return KMC_EINVAL;
+    if (flags & ~(uint32_t)(KMC_TUNE_LAUNCH | KMC_TUNE_CELLS | KMC_TUNE_PRECISION | KMC_TUNE_ADAPT))
+        return KMC_EINVAL;
+    if ((flags & KMC_TUNE_ADAPT) && cfg->adapt_levels == 0) return KMC_EINVAL;
     if (steps == 0) steps = 3;
     if (steps > 1000) return KMC_EINVAL;
 
@@ -640,6 +642,8 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     if (flags & KMC_TUNE_CELLS) kappas = {1.0, 1.25, 1.5, 2.0};
     std::vector<int32_t> precs{cfg->precision};
     if (flags & KMC_TUNE_PRECISION) precs = {KMC_FP64, KMC_FP32_SCREEN};
+    std::vector<uint32_t> thresholds{cfg->adapt_threshold};
+    if (flags & KMC_TUNE_ADAPT) thresholds = {4u, 8u, 16u, 32u};
     const bool launch = (flags & KMC_TUNE_LAUNCH) != 0;
     std::memset(out, 0, sizeof(*out));
     hipStream_t s = (hipStream_t)stream;
@@ -662,6 +666,7 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
         out->kappa[k] = kappa;
         out->precision[k] = c.precision;
         out->tile[k] = c.tile;
+        out->adapt_threshold[k] = c.adapt_levels > 0 ? c.adapt_threshold : 0u;
         out->ms_per_step[k] = NAN;
         size_t need = 0;
         kmc_ctx* ctx = nullptr;
@@ -694,42 +699,48 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
         bool ok = true;
         for (uint32_t b = 0; b < nboxes && ok; ++b)
             ok = kappa == 0.0 ? (bx[b] = boxes[b], true) : kmc_box_with_kappa(&boxes[b], kappa, &bx[b]) == KMC_OK;
-        kmc_config base = *cfg;
-        base.use_graph = 0;
-        base.profile = 0;
-        if (launch) {
-            base.block_size = 256;
-            base.tile = 0;
-        }
-        // stage 1: precision x search organisation
-        kmc_config cur = base;
-        double cur_ms = INFINITY;
-        const std::vector<int32_t> modes = launch ? std::vector<int32_t>{KMC_SEARCH_HALF, KMC_SEARCH_FULL}
-                                                  : std::vector<int32_t>{cfg->search_mode};
-        for (int32_t pr : precs)
-            for (int32_t mode : modes) {
-                kmc_config c = base;
-                c.precision = pr;
-                c.search_mode = mode;
-                const double r = trial(c, kappa, ok);
-                if (r < cur_ms) { cur_ms = r; cur = c; }
+        for (uint32_t thr : thresholds) {
+            kmc_config base = *cfg;
+            base.use_graph = 0;
+            base.profile = 0;
+            base.adapt_threshold = thr;
+            if (launch) {
+                base.block_size = 256;
+                base.tile = 0;
             }
-        if (launch && std::isfinite(cur_ms)) {
-            // stage 2: the other tile shapes; stage 3: the other block sizes
-            const kmc_config t0 = cur;
-            for (int32_t tile : {1, 2}) {
-                kmc_config c = t0;
-                c.tile = tile;
-                const double r = trial(c, kappa, ok);
-                if (r < cur_ms) { cur_ms = r; cur = c; }
+            // stage 1: precision x search organisation (adaptive bins take the
+            // full search only)
+            kmc_config cur = base;
+            double cur_ms = INFINITY;
+            std::vector<int32_t> modes{cfg->search_mode};
+            if (launch && cfg->adapt_levels == 0) modes = {KMC_SEARCH_HALF, KMC_SEARCH_FULL};
+            else if (launch) modes = {KMC_SEARCH_FULL};
+            for (int32_t pr : precs)
+                for (int32_t mode : modes) {
+                    kmc_config c = base;
+                    c.precision = pr;
+                    c.search_mode = mode;
+                    const double r = trial(c, kappa, ok);
+                    if (r < cur_ms) { cur_ms = r; cur = c; }
+                }
+            if (launch && std::isfinite(cur_ms)) {
+                // stage 2: the other tile shapes; stage 3: the other block sizes
+                const kmc_config t0 = cur;
+                for (int32_t tile : {1, 2}) {
+                    kmc_config c = t0;
+                    c.tile = tile;
+                    const double r = trial(c, kappa, ok);
+                    if (r < cur_ms) { cur_ms = r; cur = c; }
+                }
+                const kmc_config b0 = cur;
+                for (int32_t blk : {128, 512}) {
+                    kmc_config c = b0;
+                    c.block_size = blk;
+                    const double r = trial(c, kappa, ok);
+                    if (r < cur_ms) { cur_ms = r; cur = c; }
+                }
             }
-            const kmc_config b0 = cur;
-            for (int32_t blk : {128, 512}) {
-                kmc_config c = b0;
-                c.block_size = blk;
-                const double r = trial(c, kappa, ok);
-                if (r < cur_ms) { cur_ms = r; cur = c; }
-            }
+            if (status != KMC_OK) break;
         }
         if (status != KMC_OK) break;
     }
@@ -744,6 +755,7 @@ int kmc_autotune(const kmc_box* boxes, uint32_t nboxes, const kmc_config* cfg, c
     out_cfg->block_size = best_cfg.block_size;
     out_cfg->tile = best_cfg.tile;
     out_cfg->precision = best_cfg.precision;
+    out_cfg->adapt_threshold = best_cfg.adapt_threshold;
     return KMC_OK;
 }
 

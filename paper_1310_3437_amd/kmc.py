@@ -101,8 +101,10 @@ EXPORTS = ("kmc_workspace_bytes", "kmc_init", "kmc_step", "kmc_read_partners", "
 KMC_SCRATCH_BYTES = 64 << 20
 
 
-KMC_TUNE_LAUNCH, KMC_TUNE_CELLS, KMC_TUNE_PRECISION = 1, 2, 4
+KMC_TUNE_LAUNCH, KMC_TUNE_CELLS, KMC_TUNE_PRECISION, KMC_TUNE_ADAPT = 1, 2, 4, 8
 KMC_TUNE_MAX = 64
+# the layout of the structures below; the library reports its own
+KMC_ABI_VERSION = 5
 
 
 class KmcTuning(C.Structure):
@@ -115,6 +117,7 @@ class KmcTuning(C.Structure):
         ("kappa", C.c_double * KMC_TUNE_MAX),
         ("precision", C.c_int32 * KMC_TUNE_MAX),
         ("tile", C.c_int32 * KMC_TUNE_MAX),
+        ("adapt_threshold", C.c_uint32 * KMC_TUNE_MAX),
     ]
 
 
@@ -160,6 +163,9 @@ def load(path=LIB_PATH):
               "kmc_read_history", "kmc_read_time", "kmc_count_pair_tests", "kmc_get_stats", "kmc_abi_version",
               "kmc_autotune", "kmc_box_with_kappa", "kmc_init_scratch"):
         getattr(L, f).restype = C.c_int
+    if L.kmc_abi_version() != KMC_ABI_VERSION:
+        raise KmcError(f"{path}: ABI version {L.kmc_abi_version()}, this binding expects {KMC_ABI_VERSION} "
+                       "(rebuild the library)")
     _lib = L
     return L
 
@@ -287,9 +293,11 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
             if hit is not None:
                 kappa = hit["kappa"]
                 nb = [box_with_kappa(b, kappa) for b in boxes] if kappa > 0 else boxes
-                return nb, dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"],
-                                tile=hit["tile"], precision=hit["precision"]), \
-                    dict(best=hit["best"], tried=hit["tried"], cached=True)
+                cfg_hit = dict(config, search_mode=hit["search_mode"], block_size=hit["block_size"],
+                               tile=hit["tile"], precision=hit["precision"])
+                if hit.get("adapt_threshold"):
+                    cfg_hit["adapt_threshold"] = hit["adapt_threshold"]
+                return nb, cfg_hit, dict(best=hit["best"], tried=hit["tried"], cached=True)
     spc = {}
     if kinds is not None:
         kind_t = torch.as_tensor(np.asarray(kinds[0]), dtype=torch.uint8).to(device).contiguous()
@@ -303,6 +311,8 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
     pcfg = dict(config, block_size=64)
     if flags & KMC_TUNE_PRECISION:
         pcfg["precision"] = KMC_FP32_SCREEN
+    if flags & KMC_TUNE_ADAPT:
+        pcfg["adapt_threshold"] = 4   # the smallest threshold needs the largest leaf tables
     need = workspace_bytes(probe, make_config(**pcfg, **spc))
     ws = torch.empty(need + 256, dtype=torch.uint8, device=device)
     ptr = (ws.data_ptr() + 255) // 256 * 256
@@ -316,8 +326,11 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
     new_boxes = [_box_from_kmc(out_b[k], boxes[k]) for k in range(len(boxes))]
     new_cfg = dict(config, search_mode=int(out_c.search_mode), block_size=int(out_c.block_size),
                    tile=int(out_c.tile), precision=int(out_c.precision))
+    if flags & KMC_TUNE_ADAPT:
+        new_cfg["adapt_threshold"] = int(out_c.adapt_threshold)
     tried = [dict(ms_per_step=tun.ms_per_step[k], search_mode=tun.search_mode[k], block_size=tun.block_size[k],
-                  kappa=tun.kappa[k], precision=tun.precision[k], tile=tun.tile[k]) for k in range(tun.ntried)]
+                  kappa=tun.kappa[k], precision=tun.precision[k], tile=tun.tile[k],
+                  adapt_threshold=int(tun.adapt_threshold[k])) for k in range(tun.ntried)]
     if cache is not None:
         db = {}
         if os.path.exists(cache):
@@ -325,7 +338,9 @@ def autotune(boxes, state, device="cuda", flags=KMC_TUNE_LAUNCH, steps=3, cache=
                 db = json.load(fh)
         best = tried[int(tun.best)]
         db[key] = dict(search_mode=best["search_mode"], block_size=best["block_size"], kappa=best["kappa"],
-                       tile=best["tile"], precision=best["precision"], best=int(tun.best), tried=[{k: (None if isinstance(v, float) and v != v else v)
+                       tile=best["tile"], precision=best["precision"],
+                       adapt_threshold=best["adapt_threshold"] if flags & KMC_TUNE_ADAPT else 0,
+                       best=int(tun.best), tried=[{k: (None if isinstance(v, float) and v != v else v)
                                                    for k, v in t.items()} for t in tried])
         tmp = cache + ".tmp"
         with open(tmp, "w") as fh:

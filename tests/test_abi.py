@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(kmc.EXPORTS)
-    assert L.kmc_abi_version() == 4
+    assert L.kmc_abi_version() == kmc.KMC_ABI_VERSION == 5
 
 
 def test_one_hip_runtime_whatever_the_import_order():
@@ -53,6 +53,27 @@ def test_struct_sizes_match_header():
     assert C.sizeof(kmc.KmcConfig) == 96
     assert C.sizeof(kmc.KmcStats) == 136
     assert C.sizeof(kmc.KmcSpecies) == 144
+    # kmc_tuning: two u32, then per candidate (64) ms, mode, block, kappa,
+    # precision, tile, adaptive threshold
+    assert C.sizeof(kmc.KmcTuning) == 8 + 64 * (8 + 4 + 4 + 8 + 4 + 4 + 4)
+
+
+def test_autotune_rejects_bad_flags_before_touching_the_device():
+    """Unknown flags, and the adaptive-threshold flag without adaptive
+    bins, are refused by the host-side checks."""
+    L = kmc.load()
+    boxes = [_good()]
+    arr = kmc.make_boxes(boxes)
+    out_b = (kmc.KmcBox * 1)()
+    out_c = kmc.KmcConfig()
+    tun = kmc.KmcTuning()
+    fake = C.c_void_p(1 << 20)
+    for flags, cfg in ((16, {}), (kmc.KMC_TUNE_ADAPT, {}),
+                       (kmc.KMC_TUNE_ADAPT | kmc.KMC_TUNE_LAUNCH, dict(precision=kmc.KMC_FP32_SCREEN))):
+        c = kmc.make_config(**cfg)
+        rc = L.kmc_autotune(arr, 1, C.byref(c), fake, fake, C.c_size_t(1 << 20), flags, 2, None, out_b,
+                            C.byref(out_c), C.byref(tun))
+        assert rc == kmc.KMC_EINVAL, (flags, rc)
 
 
 def _ws(boxes, **cfg):

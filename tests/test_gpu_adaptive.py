@@ -139,3 +139,18 @@ def test_blobs_1e7_sampled(kmc, precision):
     got = st[:, torch.as_tensor(sel, device=st.device)].cpu().numpy()
     assert np.array_equal(got, ref_s)
     print(f"[adapt] {sel.size} sampled particles identical ({len(dense)} in cells of > 64)", flush=True)
+
+
+def test_autotuned_threshold(kmc):
+    """KMC_TUNE_ADAPT times the thresholds 4, 8, 16 and 32 and returns one of
+    them; the run with the returned configuration equals the oracle's
+    adaptive mode at that threshold."""
+    w = _adapt(I.c5_blobs(n=80_000, steps=2), 3, 8)
+    boxes, cfg, tun = kmc.autotune(w.boxes, w.state, device="cuda:0", steps=1, seed=w.seed,
+                                   flags=kmc.KMC_TUNE_LAUNCH | kmc.KMC_TUNE_ADAPT,
+                                   search_mode=kmc.KMC_SEARCH_FULL, adapt_levels=3, adapt_threshold=8)
+    assert cfg["adapt_threshold"] in (4, 8, 16, 32)
+    assert sorted({t["adapt_threshold"] for t in tun["tried"]}) == [4, 8, 16, 32]
+    assert all(t["search_mode"] == kmc.KMC_SEARCH_FULL for t in tun["tried"])
+    w.adapt_threshold = cfg["adapt_threshold"]
+    run_adaptive(kmc, w, 2, "fp64", block_size=cfg["block_size"], tile=cfg["tile"])
