@@ -180,3 +180,32 @@ def test_c5_blobs_1e7_50_steps_sampled(kmc):
     w = I.c5_blobs(steps=50)
     _sampled_every_step(kmc, w, 50, "fp32", search_mode=kmc.KMC_SEARCH_FULL, use_graph=True)
     _sampled_every_step(kmc, w, 50, "fp64", search_mode=kmc.KMC_SEARCH_FULL)
+
+
+@pytest.mark.timeout(900)
+def test_c3_sphere_1e8_200_steps_screen_equals_fp64(kmc):
+    """Ten times the headline run's length (the infalling core keeps
+    densifying, which widens the velocity spread the FP32 screen's bounds
+    must cover): the screen's and plain FP64's per-step collision counts and
+    digests, and their final FP64 states, are identical."""
+    import torch
+    w = I.c3_sphere(steps=200)
+    out = {}
+    for precision in ("fp32", "fp64"):
+        prec = kmc.KMC_FP64 if precision == "fp64" else kmc.KMC_FP32_SCREEN
+        print(f"\n[long] c3_sphere N={w.n} 200 steps {precision}", flush=True)
+        sim = kmc.Sim(w.boxes, w.state, device="cuda:0", seed=w.seed, precision=prec, history=256, use_graph=True)
+        for k in range(4):
+            sim.step(50)
+            torch.cuda.synchronize()
+            print(f"[long] {precision}: {50 * (k + 1)} steps", flush=True)
+        hn, hd = sim.history()
+        st = sim.state().cpu().numpy()
+        stats = sim.stats()
+        sim.close()
+        out[precision] = ([(int(a), int(b)) for a, b in zip(hn, hd)], _sha(st.astype("<f8")), stats)
+        print(f"[long] {precision}: {sum(a for a, _ in out[precision][0])} collisions, rechecks "
+              f"{stats['rechecks']}, fallbacks {stats['fallbacks']}", flush=True)
+    assert len(out["fp32"][0]) == 200
+    assert out["fp32"][0] == out["fp64"][0], "per-step counts or digests differ between the precisions"
+    assert out["fp32"][1] == out["fp64"][1], "final states differ between the precisions"
