@@ -16,7 +16,7 @@ constexpr int kScanTile = kScanBlock * kScanItems;
 // Per-step accumulators of the collision count, the digest and the recorded
 // candidates: one 128-byte line each, so the per-block atomics of the search
 // and the resolve spread over this many cache lines (k_advance folds them).
-constexpr int kAccLanes = 4096;
+constexpr int kAccLanes = 1024;
 // Candidates the search records per particle before the particle falls
 // back to a full search.
 constexpr int kSlots = 8;
