@@ -3,9 +3,11 @@
 Workload (the headline configuration): N = 1e8 particles uniform in a ball
 of radius 1 with radial infall v = -0.5 x + N(0, 0.1^2), reflecting sphere,
 399^3 cells of edge ~D (about three particles per cell), seeded synthetic
-input.  The plain FP64 path and the FP32-screen path each run W untimed and K
-timed steps from the same initial state, replayed from a captured hipGraph as
-a caller would run them; `value` is the FP32-screen path's particle-steps/s
+input.  The plain FP64 path and the FP32-screen path each pick their launch
+configuration with the autotuner on this input (search organisation, tile
+shape, block size: the results do not depend on them), then run W untimed
+and K timed steps from the same initial state, replayed from a captured
+hipGraph as a caller would run them; `value` is the FP32-screen path's particle-steps/s
 when that path is built, else the FP64 path's.  Their per-step pair counts
 and digests must be identical to each other and, for the headline workload,
 to the oracle's record of the same run (tests/golden/full_c3_sphere.json).
@@ -322,7 +324,7 @@ def main():
     ap.add_argument("--autotune", default=None, choices=("none", "launch", "cells"),
                     help="kmc_autotune before timing: launch (search organisation, block size; results "
                          "unchanged) or cells (also the cell edge, which changes the partner criteria); "
-                         "default cells for c4_batch, launch for c5_blobs, none otherwise")
+                         "default cells for c4_batch, launch for c3_sphere and c5_blobs, none otherwise")
     ap.add_argument("--adapt", default=None,
                     help="density-adaptive bins L,T (at most L halvings of a cell, split while it holds more than "
                          "T 8^level particles; T = auto: chosen by the autotuner); changes the neighbourhoods, so "
@@ -387,7 +389,7 @@ def main():
                             candidates=len(info["tried"]))
         desc = desc.replace("than 8 x 8^level", f"than {w.adapt_threshold} x 8^level (threshold autotuned)")
 
-    tune = args.autotune or dict(c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
+    tune = args.autotune or dict(c3_sphere="launch", c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
     paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "tuned")]
     if os.environ.get("KMC_BENCH_NO_F32") is not None:
         paths = [p for p in paths if p != "fp32"]
