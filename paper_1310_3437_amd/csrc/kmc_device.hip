@@ -1036,6 +1036,15 @@ struct Best {
     }
 };
 
+// Pairs the FP32 screen keeps in the full-neighbourhood search, decided in
+// FP64 once the tile's rows are done (a record gather inside the pair loop
+// stalls the whole wave); a lane's pairs beyond kReg are decided at once.
+struct Deferred {
+    uint32_t* sj;   // this lane's slots in LDS: sorted index of pair k at sj[64 k],
+                    // its image shift (wcode) at sj[64 (kReg + k)]
+    int n;
+};
+
 // Tile shape of a search kernel: W records staged per LDS chunk, and the
 // waves per SIMD the half- and full-neighbourhood searches are compiled for
 // (fewer waves leave more registers per wave).  The launch autotuner picks
@@ -1119,7 +1128,7 @@ struct PolF64 {
     template <bool SH>
     __device__ static void scan_best(const Plan&, const Lds& l, const uint32_t* lid, uint32_t c0, uint32_t j0,
                                      uint32_t j1, uint32_t, const Own& o, const BoxDev& B, const Group&, int wx,
-                                     int wy, int wz, int, int, Best& best)
+                                     int wy, int wz, int, int, Best& best, Deferred&)
     {
         const double sx = (double)wx * B.L[0], sy = (double)wy * B.L[1], sz = (double)wz * B.L[2];
         const double D2 = B.D2, dt = B.dt;
@@ -1460,7 +1469,7 @@ struct PolF32 {
     template <bool SH>
     __device__ static void scan_best(const Plan& p, const Lds& l, const uint32_t* lid, uint32_t c0, uint32_t j0,
                                      uint32_t j1, uint32_t i, const Own& o, const BoxDev& B, const Group& g,
-                                     int wx, int wy, int wz, int, int, Best& best)
+                                     int wx, int wy, int wz, int, int, Best& best, Deferred& d)
     {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
         for (uint32_t j = j0; j < j1; ++j) {
@@ -1477,6 +1486,12 @@ struct PolF32 {
             const float m2 = fmaf(-kdt, g2, -b);
             const float m3 = fmaf(rr - kd, g2, -(b * b));
             if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i)) {
+                if (d.n < kReg) {
+                    d.sj[64 * d.n] = j;
+                    d.sj[64 * (kReg + d.n)] = wcode(wx, wy, wz);
+                    ++d.n;
+                    continue;
+                }
                 const P64 me = p.B[i], q = p.B[j];
                 double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
                 if (SH) {
@@ -1488,6 +1503,27 @@ struct PolF32 {
                 best.screened += 1u;
                 if (accept(pq, K ? p.sp_D2[o.row + kj] : B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
             }
+        }
+    }
+    // the deferred pairs of particle i, decided in FP64 with their image shifts
+    __device__ static void decide_deferred(const Plan& p, uint32_t i, const Deferred& d, const BoxDev& B,
+                                           Best& best)
+    {
+        if (d.n == 0) return;
+        const P64 me = p.B[i];
+        const uint32_t row = kind_row(p, i);
+        for (int k = 0; k < d.n; ++k) {
+            const uint32_t j = d.sj[64 * k];
+            const uint32_t c = d.sj[64 * (kReg + k)];
+            const int wx = (int)(c & 3u) - 1, wy = (int)((c >> 2) & 3u) - 1, wz = (int)((c >> 4) & 3u) - 1;
+            const P64 q = p.B[j];
+            double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
+            if (wx != 0) rx = rx + (double)wx * B.L[0];
+            if (wy != 0) ry = ry + (double)wy * B.L[1];
+            if (wz != 0) rz = rz + (double)wz * B.L[2];
+            const PairQ pq = pair_q(rx, ry, rz, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            best.screened += 1u;
+            if (accept(pq, pair_D2(p, B, row, j), B.dt)) best.offer(pq.c2 / pq.g2, p.idB[j], j);
         }
     }
 };
@@ -1614,7 +1650,8 @@ void k_search_half(Plan p)
 // One tile of 64 cell-sorted particles (one wave), writing their partners;
 // STATS: count the pairs for the statistics.
 template <class Pol, bool STATS>
-__device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, typename Pol::Lds& lds, uint32_t* lid)
+__device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, typename Pol::Lds& lds, uint32_t* lid,
+                                                 uint32_t* dslots)
 {
     const int lane = threadIdx.x;
     const uint32_t i = tile * 64u + (uint32_t)lane;
@@ -1642,6 +1679,9 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
     best.j = -1;
     best.accepted = 0u;
     best.screened = 0u;
+    Deferred dfr;
+    dfr.sj = dslots + lane;
+    dfr.n = 0;
     uint64_t remaining = __ballot(alive);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
@@ -1677,9 +1717,11 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
                 __syncthreads();
                 const uint32_t j0 = max(ls, c0), j1 = min(le, c0 + n);
                 if (sh)
-                    Pol::template scan_best<true>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, dy, dz, best);
+                    Pol::template scan_best<true>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, dy, dz, best,
+                                                  dfr);
                 else
-                    Pol::template scan_best<false>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, dy, dz, best);
+                    Pol::template scan_best<false>(p, lds, lid, c0, j0, j1, i, own, B, gctx, wx, wy, wz, dy, dz, best,
+                                                   dfr);
                 __syncthreads();
             }
         };
@@ -1707,6 +1749,9 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
             }
         }
     }
+    if constexpr (Pol::kScreen) {
+        if (alive) Pol::decide_deferred(p, i, dfr, p.boxes[bidx], best);
+    }
     if (valid && (alive || p.adapt_L == 0)) p.partner[i] = best.j;
     if (STATS) {
         // statistics: pairs accepted (FP64) or decided in FP64 (FP32 screen)
@@ -1723,7 +1768,8 @@ void k_search_full(Plan p)
 {
     __shared__ typename Pol::Lds lds;
     __shared__ uint32_t lid[Pol::W];
-    search_full_tile<Pol, true>(p, xcd_tile(blockIdx.x, gridDim.x), lds, lid);
+    __shared__ uint32_t dslots[Pol::kScreen ? 2 * kReg * 64 : 1];
+    search_full_tile<Pol, true>(p, xcd_tile(blockIdx.x, gridDim.x), lds, lid, dslots);
 }
 
 // Whole-step FP64 search, by the full-neighbourhood organisation, when a
@@ -1743,7 +1789,7 @@ void k_fallback_full(Plan p)
     __shared__ uint32_t lid[Pol::W];
     if (p.ctl->overflow == 0u) return;
     const uint32_t ntiles = (p.N + 63u) / 64u;
-    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) search_full_tile<Pol, false>(p, t, lds, lid);
+    for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) search_full_tile<Pol, false>(p, t, lds, lid, nullptr);
 }
 
 // --------------------------------------------------------------------------
