@@ -324,7 +324,8 @@ def main():
     ap.add_argument("--autotune", default=None, choices=("none", "launch", "cells"),
                     help="kmc_autotune before timing: launch (search organisation, block size; results "
                          "unchanged) or cells (also the cell edge, which changes the partner criteria); "
-                         "default cells for c4_batch, launch for c3_sphere and c5_blobs, none otherwise")
+                         "default cells for c4_batch, launch for c3_sphere and c5_blobs, none otherwise, "
+                         "and none whenever --search is given (it fixes the organisation)")
     ap.add_argument("--adapt", default=None,
                     help="density-adaptive bins L,T (at most L halvings of a cell, split while it holds more than "
                          "T 8^level particles; T = auto: chosen by the autotuner); changes the neighbourhoods, so "
@@ -359,6 +360,7 @@ def main():
         raise SystemExit(f"bench.py: unknown workload {args.workload}")
     n_arg = args.n if args.n is not None else full[args.workload]
     t0 = time.perf_counter()
+    search_given = args.search is not None
     adapt, adapt_auto = None, False
     if args.adapt:
         lv, th = args.adapt.split(",")
@@ -389,7 +391,8 @@ def main():
                             candidates=len(info["tried"]))
         desc = desc.replace("than 8 x 8^level", f"than {w.adapt_threshold} x 8^level (threshold autotuned)")
 
-    tune = args.autotune or dict(c3_sphere="launch", c4_batch="cells", c5_blobs="launch").get(args.workload, "none")
+    tune = args.autotune or ("none" if search_given else
+                             dict(c3_sphere="launch", c4_batch="cells", c5_blobs="launch").get(args.workload, "none"))
     paths = [p for p in args.paths.split(",") if p in ("fp64", "fp32", "tuned")]
     if os.environ.get("KMC_BENCH_NO_F32") is not None:
         paths = [p for p in paths if p != "fp32"]
