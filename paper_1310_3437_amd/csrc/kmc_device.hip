@@ -1038,10 +1038,11 @@ struct Best {
 
 // Pairs the FP32 screen keeps in the full-neighbourhood search, decided in
 // FP64 once the tile's rows are done (a record gather inside the pair loop
-// stalls the whole wave); a lane's pairs beyond kReg are decided at once.
+// stalls the whole wave); a lane's pairs beyond kDefer are decided at once.
+constexpr int kDefer = 4;
 struct Deferred {
     uint32_t* sj;   // this lane's slots in LDS: sorted index of pair k at sj[64 k],
-                    // its image shift (wcode) at sj[64 (kReg + k)]
+                    // its image shift (wcode) at sj[64 (kDefer + k)]
     int n;
 };
 
@@ -1486,9 +1487,9 @@ struct PolF32 {
             const float m2 = fmaf(-kdt, g2, -b);
             const float m3 = fmaf(rr - kd, g2, -(b * b));
             if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i)) {
-                if (d.n < kReg) {
+                if (d.n < kDefer) {
                     d.sj[64 * d.n] = j;
-                    d.sj[64 * (kReg + d.n)] = wcode(wx, wy, wz);
+                    d.sj[64 * (kDefer + d.n)] = wcode(wx, wy, wz);
                     ++d.n;
                     continue;
                 }
@@ -1514,7 +1515,7 @@ struct PolF32 {
         const uint32_t row = kind_row(p, i);
         for (int k = 0; k < d.n; ++k) {
             const uint32_t j = d.sj[64 * k];
-            const uint32_t c = d.sj[64 * (kReg + k)];
+            const uint32_t c = d.sj[64 * (kDefer + k)];
             const int wx = (int)(c & 3u) - 1, wy = (int)((c >> 2) & 3u) - 1, wz = (int)((c >> 4) & 3u) - 1;
             const P64 q = p.B[j];
             double rx = q.x - me.x, ry = q.y - me.y, rz = q.z - me.z;
@@ -1680,8 +1681,9 @@ __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, t
     best.accepted = 0u;
     best.screened = 0u;
     Deferred dfr;
-    dfr.sj = dslots + lane;
+    dfr.sj = nullptr;
     dfr.n = 0;
+    if constexpr (Pol::kScreen) dfr.sj = dslots + lane;
     uint64_t remaining = __ballot(alive);
     while (remaining) {
         const int lead = __ffsll((unsigned long long)remaining) - 1;
@@ -1768,7 +1770,7 @@ void k_search_full(Plan p)
 {
     __shared__ typename Pol::Lds lds;
     __shared__ uint32_t lid[Pol::W];
-    __shared__ uint32_t dslots[Pol::kScreen ? 2 * kReg * 64 : 1];
+    __shared__ uint32_t dslots[Pol::kScreen ? 2 * kDefer * 64 : 1];
     search_full_tile<Pol, true>(p, xcd_tile(blockIdx.x, gridDim.x), lds, lid, dslots);
 }
 
