@@ -1450,9 +1450,7 @@ struct PolF32 {
         // the staged record for a kept pair alone
         const float4* rp = l.a + (j0 - c0);
         const float4* const re = rp + (j1 > j0 ? j1 - j0 : 0u);
-        for (; rp < re; ++rp) {
-            const float4 qa = rp[0];
-            const float4 qb = rp[W];
+        auto test = [&](const float4& qa, const float4& qb) {
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
             const float gx = qa.w - o.vx, gy = qb.x - o.vy, gz = qb.y - o.vz;
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
@@ -1462,7 +1460,21 @@ struct PolF32 {
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
             const float m3 = fmaf(rr - kd, g2, -(b * b));
-            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0)) f.add(p, i, __float_as_uint(qb.w), wcode(wx, wy, wz));
+            return (mb <= tb0) & (m2 <= tt0) & (m3 <= tc0);
+        };
+        // two records per iteration: one loop test and one branch on the
+        // kept pairs per two pair tests, and both LDS reads in flight
+        for (; rp + 1 < re; rp += 2) {
+            const float4 qa0 = rp[0], qb0 = rp[W], qa1 = rp[1], qb1 = rp[W + 1];
+            const bool k0 = test(qa0, qb0), k1 = test(qa1, qb1);
+            if (k0 | k1) {
+                if (k0) f.add(p, i, __float_as_uint(qb0.w), wcode(wx, wy, wz));
+                if (k1) f.add(p, i, __float_as_uint(qb1.w), wcode(wx, wy, wz));
+            }
+        }
+        if (rp < re) {
+            const float4 qa = rp[0], qb = rp[W];
+            if (test(qa, qb)) f.add(p, i, __float_as_uint(qb.w), wcode(wx, wy, wz));
         }
     }
     // full neighbourhood: every pair the screen cannot reject is decided in
@@ -1473,7 +1485,7 @@ struct PolF32 {
                                      int wx, int wy, int wz, int, int, Best& best, Deferred& d)
     {
         const float tb0 = g.t.tb0, tb1 = g.t.tb1, tt0 = g.t.tt0, kdt = g.t.kdt, tc0 = g.t.tc0, kD2 = g.t.kD2;
-        for (uint32_t j = j0; j < j1; ++j) {
+        auto test = [&](uint32_t j) {
             const float4 qa = l.a[j - c0];
             const float4 qb = l.b[j - c0];
             const float rx = qa.x - o.x, ry = qa.y - o.y, rz = qa.z - o.z;
@@ -1481,30 +1493,40 @@ struct PolF32 {
             const float b = fmaf(rz, gz, fmaf(ry, gy, rx * gx));
             const float g2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
             const float rr = fmaf(rz, rz, fmaf(ry, ry, rx * rx));
-            const uint32_t kj = K ? __float_as_uint(qb.z) : 0u;
-            const float kd = K ? l.kd2[o.row + kj] : kD2;
+            const float kd = K ? l.kd2[o.row + __float_as_uint(qb.z)] : kD2;
             const float mb = fmaf(-tb1, g2, b);
             const float m2 = fmaf(-kdt, g2, -b);
             const float m3 = fmaf(rr - kd, g2, -(b * b));
-            if ((mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i)) {
-                if (d.n < kDefer) {
-                    d.sj[64 * d.n] = j;
-                    d.sj[64 * (kDefer + d.n)] = wcode(wx, wy, wz);
-                    ++d.n;
-                    continue;
-                }
-                const P64 me = p.B[i], q = p.B[j];
-                double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
-                if (SH) {
-                    rx6 = rx6 + (double)wx * B.L[0];
-                    ry6 = ry6 + (double)wy * B.L[1];
-                    rz6 = rz6 + (double)wz * B.L[2];
-                }
-                const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
-                best.screened += 1u;
-                if (accept(pq, K ? p.sp_D2[o.row + kj] : B.D2, B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
+            return (mb <= tb0) & (m2 <= tt0) & (m3 <= tc0) & (j != i);
+        };
+        // a kept pair: recorded for the end of the tile, or decided at once
+        auto take = [&](uint32_t j) {
+            if (d.n < kDefer) {
+                d.sj[64 * d.n] = j;
+                d.sj[64 * (kDefer + d.n)] = wcode(wx, wy, wz);
+                ++d.n;
+                return;
+            }
+            const P64 me = p.B[i], q = p.B[j];
+            double rx6 = q.x - me.x, ry6 = q.y - me.y, rz6 = q.z - me.z;
+            if (SH) {
+                rx6 = rx6 + (double)wx * B.L[0];
+                ry6 = ry6 + (double)wy * B.L[1];
+                rz6 = rz6 + (double)wz * B.L[2];
+            }
+            const PairQ pq = pair_q(rx6, ry6, rz6, q.vx - me.vx, q.vy - me.vy, q.vz - me.vz);
+            best.screened += 1u;
+            if (accept(pq, pair_D2(p, B, o.row, j), B.dt)) best.offer(pq.c2 / pq.g2, lid[j - c0], j);
+        };
+        uint32_t j = j0;
+        for (; j + 1 < j1; j += 2) {   // two records per iteration, as in scan
+            const bool k0 = test(j), k1 = test(j + 1);
+            if (k0 | k1) {
+                if (k0) take(j);
+                if (k1) take(j + 1);
             }
         }
+        if (j < j1 && test(j)) take(j);
     }
     // the deferred pairs of particle i, decided in FP64 with their image shifts
     __device__ static void decide_deferred(const Plan& p, uint32_t i, const Deferred& d, const BoxDev& B,
