@@ -100,6 +100,21 @@ __device__ __forceinline__ bool accept(const PairQ& q, double D2, double dt)
     return (q.g2 > 0.0) & (q.b <= 0.0) & (-q.b <= dt * q.g2) & (q.c2 < D2 * q.g2);
 }
 
+// Full 128-bit product of two 64-bit words from four 32x32 partial
+// products (schoolbook); each partial product plus a 64-bit addend fits in
+// 64 bits, so every step is one 32x32+64 multiply-add and the low word
+// reuses the partial products instead of multiplying again.
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t& hi, uint64_t& lo)
+{
+    const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+    const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+    const uint64_t p00 = (uint64_t)a0 * b0;
+    const uint64_t p01 = (uint64_t)a0 * b1 + (p00 >> 32);
+    const uint64_t p10 = (uint64_t)a1 * b0 + (uint32_t)p01;
+    hi = (uint64_t)a1 * b1 + (p01 >> 32) + (p10 >> 32);
+    lo = (p10 << 32) | (uint32_t)p00;
+}
+
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): two 64x64->128
 // multiplications per round, Weyl-sequence key schedule.
 __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1)
@@ -109,8 +124,9 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         if (r > 0) { k0 += w0; k1 += w1; }
-        uint64_t hi0 = __umul64hi(m0, c[0]), lo0 = m0 * c[0];
-        uint64_t hi1 = __umul64hi(m1, c[2]), lo1 = m1 * c[2];
+        uint64_t hi0, lo0, hi1, lo1;
+        mul_wide(m0, c[0], hi0, lo0);
+        mul_wide(m1, c[2], hi1, lo1);
         uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
         c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
     }
