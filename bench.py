@@ -56,9 +56,10 @@ FLOP_PER_PAIR_TEST = 37
 PEAK_FP32_TFLOPS = 157.3
 PEAK_FP64_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
-# Algorithmic HBM bytes per particle-step of the whole FP64 step (bin 32,
-# scan ~5, sorted copy 116, search 52, resolve/scatter/stream 110).
-STEP_BYTES_PER_PARTICLE = 315
+# Algorithmic HBM bytes per particle-step of the whole FP64 step on the
+# uniform grid (bin 28: slot and count, scan ~5, sorted copy 112, search 52,
+# resolve/scatter/stream 110); the cell is recomputed, not stored.
+STEP_BYTES_PER_PARTICLE = 307
 # Algorithmic HBM bytes per particle of one search launch: read the sorted
 # records once (FP64 48 B, FP32 screen 24 B) and write the result (4 B).
 SEARCH_BYTES_PER_PARTICLE = {"fp64": 52, "fp32_screen": 28}

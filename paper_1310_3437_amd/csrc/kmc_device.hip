@@ -339,21 +339,25 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
 // the previous step's cell order, so neighbouring lanes mostly share a cell
 // and each run of equal cells takes its slots with one atomic issued by the
 // run's first lane.  Every lane of the wave must call this.
+// Global cell of a particle at (x, y, z) in box B; absorbed particles go to
+// the box's extra cell after its grid.  The sorted copy and the leaf count
+// recompute it from the same stored position instead of reading it back.
+__device__ __forceinline__ uint32_t cell_of(const BoxDev& B, double x, double y, double z, bool gone)
+{
+    if (gone) return B.coff + (uint32_t)B.nc[0] * (uint32_t)B.nc[1] * (uint32_t)B.nc[2];
+    const int cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
+    const int cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
+    const int cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
+    return B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
+}
+
 __device__ __forceinline__ void bin_particle(const Plan& p, uint32_t i, bool valid, const BoxDev& B, double x,
                                              double y, double z, bool gone)
 {
     uint32_t c = 0xFFFFFFFFu;
     if (valid) {
-        if (gone) {
-            // the box's cell of absorbed particles, after its grid
-            c = B.coff + (uint32_t)B.nc[0] * (uint32_t)B.nc[1] * (uint32_t)B.nc[2];
-        } else {
-            const int cx = cell1(x, B.lo[0], B.inv_h[0], B.nc[0]);
-            const int cy = cell1(y, B.lo[1], B.inv_h[1], B.nc[1]);
-            const int cz = cell1(z, B.lo[2], B.inv_h[2], B.nc[2]);
-            c = B.coff + (uint32_t)cx + (uint32_t)B.nc[0] * ((uint32_t)cy + (uint32_t)B.nc[1] * (uint32_t)cz);
-        }
-        p.cell[i] = c;
+        c = cell_of(B, x, y, z, gone);
+        if (p.adapt_L > 0) p.cell[i] = c;   // the leaf count reads it back
     }
     const int lane = threadIdx.x & 63;
     const uint64_t live = __ballot(valid);
@@ -666,18 +670,21 @@ __global__ void k_scatter(Plan p)
     float vm = 0.f;
     bool outside = false;
     double vx = 0.0, vy = 0.0, vz = 0.0;
-    if (valid) {
-        const uint32_t c = p.cell[i];
-        uint32_t d = p.start[c] + p.slot[i];
+    // the particle's box; one box (no per-particle index): the same for the
+    // whole grid, read through scalar loads
+    auto body = [&](const BoxDev& B) {
+        const uint32_t id = p.idA[i];
         P64 r;
         r.x = p.A[i];
         r.y = p.A[N + i];
         r.z = p.A[2 * N + i];
+        const uint32_t c = p.adapt_L > 0 ? p.cell[i] : cell_of(B, r.x, r.y, r.z, (id & kGone) != 0u);
+        uint32_t d = p.start[c] + p.slot[i];
         if (p.adapt_L > 0) {
             // adaptive bins: leaf-sorted inside a split cell
             const uint32_t lvl = p.level[c];
             if (lvl) {
-                const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, r.x, r.y, r.z);
+                const uint32_t code = leaf_code(B, p.adapt_L, lvl, r.x, r.y, r.z);
                 d = p.start[c] + p.pool[p.pool_base[c] + code] + p.leaf_slot[i];
             }
         }
@@ -685,7 +692,6 @@ __global__ void k_scatter(Plan p)
         r.vy = vy = p.A[4 * N + i];
         r.vz = vz = p.A[5 * N + i];
         p.B[d] = r;
-        const uint32_t id = p.idA[i];
         p.idB[d] = id;
         if (p.spA) p.spB[d] = p.spA[i];
         if (id & kGone) vx = vy = vz = 0.0;   // not in the gas: no part in the adaptive step
@@ -701,7 +707,6 @@ __global__ void k_scatter(Plan p)
             // just past a face of a grid that fits it exactly) stay within
             // the slack and are ignored.
             if (!(id & kGone)) {
-                const BoxDev& B = box_of(p, i);
                 outside = !(r.x >= B.lo[0] && r.x <= B.hi[0] && r.y >= B.lo[1] && r.y <= B.hi[1] &&
                             r.z >= B.lo[2] && r.z <= B.hi[2]);
                 if (outside) {
@@ -711,6 +716,10 @@ __global__ void k_scatter(Plan p)
                 }
             }
         }
+    };
+    if (valid) {
+        if (p.boxidx) body(p.boxes[p.boxidx[i]]);
+        else body(p.boxes[0]);
     }
     __shared__ float wmax[16];
     __shared__ unsigned long long wv2[16];
@@ -1686,8 +1695,10 @@ void k_search_half(Plan p)
 // every pair twice but records nothing, so it suits dense cells with many
 // acceptable partners per particle, where the candidate lists of the
 // half-neighbourhood search overflow.  Rows and staging as in k_search_half.
-// One tile of 64 cell-sorted particles (one wave), writing their partners;
-// STATS: count the pairs for the statistics.
+// Under the FP32 screen the kept pairs wait in LDS (Deferred) and are decided
+// in FP64 after the last row.  One tile of 64 cell-sorted particles (one
+// wave), writing their partners; dslots: kDefer * 2 * 64 words of LDS for
+// the FP32 screen (unused in FP64); STATS: count the pairs for the statistics.
 template <class Pol, bool STATS>
 __device__ __forceinline__ void search_full_tile(const Plan& p, uint32_t tile, typename Pol::Lds& lds, uint32_t* lid,
                                                  uint32_t* dslots)

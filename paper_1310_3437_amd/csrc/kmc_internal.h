@@ -115,7 +115,8 @@ struct Plan {
     ScreenBounds* box_sb;          // per box [kSpanClasses]: FP32 screen thresholds this step
     uint32_t* idA;
     uint32_t* idB;
-    uint32_t* cell;                // per particle in A order: global cell
+    uint32_t* cell;                // per particle in A order: global cell (adaptive bins only;
+                                   // otherwise recomputed from the position where needed)
     uint32_t* slot;                // per particle in A order: rank inside its cell
     int32_t* partner;              // per sorted particle: sorted index of partner or -1
     uint32_t* sl_cnt;              // per sorted particle: entries posted to its candidate list
