@@ -340,8 +340,9 @@ __global__ void k_read_state(Plan p, double* __restrict__ out)
 // and each run of equal cells takes its slots with one atomic issued by the
 // run's first lane.  Every lane of the wave must call this.
 // Global cell of a particle at (x, y, z) in box B; absorbed particles go to
-// the box's extra cell after its grid.  The sorted copy and the leaf count
-// recompute it from the same stored position instead of reading it back.
+// the box's extra cell after its grid.  On the uniform grid the sorted copy
+// recomputes it from the same stored position instead of reading it back;
+// with adaptive bins the binning stores it for the leaf count and the copy.
 __device__ __forceinline__ uint32_t cell_of(const BoxDev& B, double x, double y, double z, bool gone)
 {
     if (gone) return B.coff + (uint32_t)B.nc[0] * (uint32_t)B.nc[1] * (uint32_t)B.nc[2];
