@@ -190,7 +190,9 @@ size_t layout(Plan& p, char* base, uint32_t nboxes, const kmc_config& cfg, const
     p.box_sb = (ScreenBounds*)take(sizeof(ScreenBounds) * kSpanClasses * nboxes);
     p.idA = (uint32_t*)take(4 * N);
     p.idB = (uint32_t*)take(4 * N);
-    p.cell = (uint32_t*)take(4 * N);
+    // the binned cell is stored only for adaptive bins (the uniform grid's
+    // sorted copy recomputes it from the position)
+    p.cell = cfg.adapt_levels > 0 ? (uint32_t*)take(4 * N) : nullptr;
     p.slot = (uint32_t*)take(4 * N);
     p.partner = (int32_t*)take(4 * N);
     p.sl_cnt = (uint32_t*)take(4 * N);
