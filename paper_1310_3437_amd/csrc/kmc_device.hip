@@ -607,17 +607,37 @@ __global__ __launch_bounds__(64) void k_refined_prep(Plan p)
 }
 
 // Adaptive bins: each particle of a split cell counts itself into its leaf;
-// the returned value is its rank in the leaf.
+// the returned value is its rank in the leaf.  The state is in the previous
+// step's leaf order, so neighbouring lanes mostly share a leaf: each run of
+// equal leaves takes its ranks with one atomic issued by the run's first lane
+// (as the binning does for cells).  Every lane of the wave takes part.
 __global__ void k_leaf_count(Plan p)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= p.N) return;
-    const uint32_t c = p.cell[i];
-    const uint32_t lvl = p.level[c];
-    if (lvl == 0u) return;
-    const size_t N = p.N;
-    const uint32_t code = leaf_code(box_of(p, i), p.adapt_L, lvl, p.A[i], p.A[N + i], p.A[2 * N + i]);
-    p.leaf_slot[i] = atomicAdd(&p.pool[p.pool_base[c] + code], 1u);
+    const uint32_t kNone = 0xFFFFFFFFu;
+    uint32_t key = kNone;   // the particle's leaf counter in the pool (none: its cell is not split)
+    if (i < p.N) {
+        const uint32_t c = p.cell[i];
+        const uint32_t lvl = p.level[c];
+        if (lvl != 0u) {
+            const size_t N = p.N;
+            key = p.pool_base[c] + leaf_code(box_of(p, i), p.adapt_L, lvl, p.A[i], p.A[N + i], p.A[2 * N + i]);
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const bool counted = key != kNone;
+    const uint32_t prev = __shfl_up(key, 1, 64);
+    const bool cont = counted && lane > 0 && prev == key;   // same leaf as the lane before
+    const uint64_t H = __ballot(counted && !cont);          // first lanes of runs
+    const uint64_t E = __ballot(!cont);                     // lanes that do not continue a run
+    const uint64_t upto = (2ull << lane) - 1ull;            // lanes 0..lane
+    const uint64_t after = E & ~upto;
+    const int next = after ? __ffsll((unsigned long long)after) - 1 : 64;
+    uint32_t base = 0;
+    if (counted && !cont) base = atomicAdd(&p.pool[key], (unsigned int)(next - lane));
+    const int my_head = counted ? 63 - __clzll((long long)(H & upto)) : lane;
+    base = (uint32_t)__shfl((int)base, my_head, 64);
+    if (counted) p.leaf_slot[i] = base + (uint32_t)(lane - my_head);
 }
 
 // Adaptive bins, per split cell (one wave each): the exclusive prefix of its
