@@ -510,8 +510,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
     if (p.adapt_L > 0) {
         // adaptive bins: this step's split level of every cell from its count;
         // split cells are listed and claim their leaf tables (one pair of
-        // atomics per wave: its split cells take consecutive list entries and
-        // pool ranges, in lane order)
+        // atomics per block, on two counters that every block shares: the
+        // block's split cells take consecutive list entries and pool ranges,
+        // in thread order)
         uint64_t lv = 0;
         uint32_t nsplit = 0, need = 0;
 #pragma unroll
@@ -536,13 +537,35 @@ __global__ __launch_bounds__(kScanBlock) void k_scan_down(Plan p)
                 xn += yn;
             }
         }
-        uint32_t bs = 0, bn = 0;
-        if (lane == 63 && xs) {
-            bs = atomicAdd(&p.ctl->refined_count, xs);
-            bn = atomicAdd(&p.ctl->pool_used, xn);
+        __shared__ uint32_t wsum[2][kScanBlock / 64];
+        const int wid = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+        if (lane == 63) {
+            wsum[0][wid] = xs;
+            wsum[1][wid] = xn;
         }
-        uint32_t rs = (uint32_t)__shfl((int)bs, 63, 64) + xs - nsplit;
-        uint32_t rn = (uint32_t)__shfl((int)bn, 63, 64) + xn - need;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t ts = 0, tn = 0;
+            for (int w = 0; w < nw; ++w) {
+                ts += wsum[0][w];
+                tn += wsum[1][w];
+            }
+            uint32_t bs = 0, bn = 0;
+            if (ts) {
+                bs = atomicAdd(&p.ctl->refined_count, ts);
+                bn = atomicAdd(&p.ctl->pool_used, tn);
+            }
+            for (int w = 0; w < nw; ++w) {   // each wave's first entry and pool offset
+                const uint32_t a = wsum[0][w], b = wsum[1][w];
+                wsum[0][w] = bs;
+                wsum[1][w] = bn;
+                bs += a;
+                bn += b;
+            }
+        }
+        __syncthreads();
+        uint32_t rs = wsum[0][wid] + xs - nsplit;
+        uint32_t rn = wsum[1][wid] + xn - need;
 #pragma unroll
         for (int k = 0; k < kScanItems; ++k) {
             const uint32_t l = (uint32_t)(lv >> (8 * k)) & 0xFFu;
