@@ -234,6 +234,37 @@ def test_adaptive_time_step_batch_and_sphere(kmc, precision):
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
+def test_paper_time_step_full_search_many_kept_pairs(kmc, precision):
+    """Section 1's own regime (dt = dx / v_max, no cap below it) gives each
+    particle many acceptable partners per step; with the full search every
+    lane then keeps more pairs than its deferred slots, so both the deferred
+    FP64 decisions and the immediate ones run (FP32 screen), in graph
+    replay, and the result is still the oracle's."""
+    # the Fig. 1 gas (one speed, random directions) at three particles per
+    # cell: about 11 acceptable partners per particle and step
+    w = I.ppc_sweep_case(n=100_000, ppc=3.0)
+    run_parity(kmc, w, 3, precision=precision, search_mode=kmc.KMC_SEARCH_FULL, use_graph=True)
+    st = run_parity.last_stats
+    # pairs decided in FP64 (FP32 screen) or accepted (FP64), per particle-step
+    per = st["candidates"] / (w.n * 3)
+    print(f"[parity] decided or accepted pairs per particle-step {per:.2f}", flush=True)
+    assert per > 5.0, per   # well above the four deferred slots of a lane
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_paper_time_step_half_search_overflow_paths(kmc, precision):
+    """The same gas with the half-neighbourhood search: lanes keep more
+    pairs than their register slots (the overflow pair list), particles
+    collect more candidates than their list slots (the FP64 re-search), or
+    the whole step falls back to the FP64 search; every path must still give
+    the oracle's result."""
+    w = I.ppc_sweep_case(n=100_000, ppc=3.0)
+    run_parity(kmc, w, 3, precision=precision, search_mode=kmc.KMC_SEARCH_HALF)
+    st = run_parity.last_stats
+    assert st["rechecks"] > 0 or st["fallbacks"] > 0, st
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
 def test_full_neighbourhood_search_mode(kmc, precision):
     """KMC_SEARCH_FULL (running minimum over the whole neighbourhood, no
     candidate lists) gives the oracle's result on every workload shape."""
